@@ -1,0 +1,347 @@
+"""Seeded synthetic convex-QP instances.
+
+This module only draws problem data.  It holds none of the solver's
+arithmetic: no bound mapping, no projections, no norms.  Both the HIP path
+and the CPU oracle are fed from here, so it must stay free of anything either
+of them computes.
+
+A QP is stated as in the paper's problem statement (Section 2, eq. QP):
+
+    minimize   1/2 x^T Q x + c^T x
+    subject to A x (sense) b   row-wise, sense in {'E', 'G', 'L'}
+               lb <= x <= ub
+
+Q is stored as full symmetric CSR (both triangles) or None (Q = 0).
+Every generator is seeded by ``SeedSequence([260223967, family, instance])``
+so an instance is reproducible from its family id and instance id alone.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+SEED_ROOT = 260223967
+
+# family ids used in the seed sequence
+FAM_RANDOM_SMALL = 0      # n=1000 random sparse QP (B^T B + 1e-2 I)
+FAM_LARGE_SPARSE = 1      # n=1e6 diagonally dominant sparse QP
+FAM_PORTFOLIO = 2         # factor-model portfolio, diagonal Q
+FAM_TINY = 10             # tiny QPs for brute-force pins
+FAM_LP = 11               # tiny LPs (Q = 0)
+FAM_EQ = 12               # equality-only, unboxed QPs (dense KKT pins)
+FAM_MIXED = 13            # medium QPs with free, one-sided and fixed variables
+
+
+@dataclass
+class QP:
+    """One problem instance in CSR form (int64 row pointers, int32 columns)."""
+
+    n: int
+    m: int
+    Q: sp.csr_matrix | None
+    A: sp.csr_matrix
+    c: np.ndarray
+    b: np.ndarray
+    sense: bytes
+    lb: np.ndarray
+    ub: np.ndarray
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    def csr_arrays(self, M):
+        """(rowptr int64, col int32, val float64) of a CSR matrix, C-contiguous."""
+        M = M.tocsr()
+        M.sum_duplicates()
+        M.sort_indices()
+        return (np.ascontiguousarray(M.indptr, dtype=np.int64),
+                np.ascontiguousarray(M.indices, dtype=np.int32),
+                np.ascontiguousarray(M.data, dtype=np.float64))
+
+    @property
+    def nnz_Q(self) -> int:
+        return 0 if self.Q is None else int(self.Q.nnz)
+
+    @property
+    def nnz_A(self) -> int:
+        return int(self.A.nnz)
+
+
+def rng_for(family: int, instance: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, family, instance]))
+
+
+def _csr(M) -> sp.csr_matrix:
+    M = sp.csr_matrix(M)
+    M.sum_duplicates()
+    M.sort_indices()
+    M.indptr = M.indptr.astype(np.int64)
+    M.indices = M.indices.astype(np.int32)
+    return M
+
+
+def _sparse_normal(rng, rows, cols, density, scale=1.0):
+    return sp.random(rows, cols, density=density, format="csr", random_state=rng,
+                     data_rvs=lambda k: rng.normal(0.0, scale, size=k))
+
+
+# ---------------------------------------------------------------------------
+# the workload families
+# ---------------------------------------------------------------------------
+
+def random_small(instance: int = 0, n: int = 1000, m: int | None = None,
+                 infeasible: bool = False) -> QP:
+    """Tiny random convex QP: Q = B^T B + 1e-2 I with B (n/2 x n) at 0.5 %
+    density, A (n/2 x n) at 1 % density, N(0,1) entries; first half of the
+    rows '=', second half '>='; box [-1, 1]; b = A x0 with x0 ~ U(-0.5, 0.5),
+    minus U(0, 0.1) slack on the '>=' rows.
+
+    For n other than 1000 the per-row nonzero counts of the n=1000 case are
+    kept (B: 5 per row, A: 10 per row), so that B^T B stays sparse.
+
+    ``infeasible`` copies row 0 onto row 1 and sets b1 = b0 + 1 (both '=')
+    so that no x satisfies both rows.
+    """
+    rng = rng_for(FAM_RANDOM_SMALL, instance)
+    m = n // 2 if m is None else m
+    dB = 0.005 if n == 1000 else 5.0 / n
+    dA = 0.01 if n == 1000 else 10.0 / n
+    B = _sparse_normal(rng, n // 2, n, dB)
+    Q = _csr(B.T @ B + 1e-2 * sp.identity(n, format="csr"))
+    A = _sparse_normal(rng, m, n, dA).tolil()
+    c = rng.normal(size=n)
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    ne = m // 2
+    sense = np.array([ord("E")] * ne + [ord("G")] * (m - ne), dtype=np.uint8)
+    if infeasible:
+        A[1, :] = A[0, :]
+    A = _csr(A)
+    b = A @ x0
+    b[ne:] -= rng.uniform(0.0, 0.1, size=m - ne)
+    if infeasible:
+        b[1] = b[0] + 1.0
+    return QP(n=n, m=m, Q=Q, A=A, c=c, b=b, sense=sense.tobytes(),
+              lb=np.full(n, -1.0), ub=np.full(n, 1.0),
+              name=f"random_small_n{n}" + ("_infeasible" if infeasible else ""),
+              meta={"x0": x0})
+
+
+def large_sparse(instance: int = 0, n: int = 1_000_000, m: int | None = None,
+                 offdiag_pairs_per_row: int = 5, a_nnz_per_row: int = 8,
+                 infeasible: bool = False) -> QP:
+    """Large sparse QP: n variables, m = n/2 rows (first half '=', second half
+    '>=').  Q: n*offdiag_pairs_per_row random (i, j), i != j, N(0,1) values,
+    symmetrised (about 2*offdiag_pairs_per_row off-diagonals per row), with
+    the diagonal set to the row's absolute off-diagonal sum + 0.1 (strictly
+    diagonally dominant, hence SPD).  A: a_nnz_per_row distinct uniform
+    columns per row, N(0,1).  Box [0, 10]; c ~ N(0,1); b = A x0, x0 ~ U(0,5).
+
+    ``infeasible`` overwrites an '=' row r2 with '=' row r1 and sets
+    b[r2] = b[r1] + 1.
+    """
+    rng = rng_for(FAM_LARGE_SPARSE, instance)
+    m = n // 2 if m is None else m
+    npair = n * offdiag_pairs_per_row
+    i = rng.integers(0, n, size=npair)
+    j = rng.integers(0, n - 1, size=npair)
+    j = j + (j >= i)                       # uniform over j != i
+    v = rng.normal(size=npair)
+    S = sp.coo_matrix((v, (i, j)), shape=(n, n))
+    Qoff = _csr(S + S.T)
+    diag = np.asarray(abs(Qoff).sum(axis=1)).ravel() + 0.1
+    Q = _csr(Qoff + sp.diags(diag))
+
+    k = a_nnz_per_row
+    cols = rng.integers(0, n, size=(m, k))
+    while True:
+        srt = np.sort(cols, axis=1)
+        bad = np.nonzero((srt[:, 1:] == srt[:, :-1]).any(axis=1))[0]
+        if bad.size == 0:
+            break
+        cols[bad] = rng.integers(0, n, size=(bad.size, k))
+    vals = rng.normal(size=(m, k))
+    rows = np.repeat(np.arange(m), k)
+    A = sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(m, n))
+    c = rng.normal(size=n)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    ne = m // 2
+    sense = np.array([ord("E")] * ne + [ord("G")] * (m - ne), dtype=np.uint8)
+    meta = {}
+    if infeasible:
+        r1, r2 = rng.choice(ne, size=2, replace=False)
+        A = A.tolil()
+        A[r2, :] = A[r1, :]
+        meta["rows"] = (int(r1), int(r2))
+    A = _csr(A)
+    b = A @ x0
+    if infeasible:
+        r1, r2 = meta["rows"]
+        b[r2] = b[r1] + 1.0
+    return QP(n=n, m=m, Q=Q, A=A, c=c, b=b, sense=sense.tobytes(),
+              lb=np.zeros(n), ub=np.full(n, 10.0),
+              name=f"large_sparse_n{n}" + ("_infeasible" if infeasible else ""),
+              meta=meta)
+
+
+def portfolio(instance: int = 0, n_assets: int = 200_000, k_factors: int = 1000,
+              f_density: float = 0.01) -> QP:
+    """Factor-model portfolio QP with diagonal Q.  Variables: weights w
+    (n_assets) then factor exposures f (k_factors).  Q = diag(d) on w,
+    d ~ U(0.01, 0.1), and I on f.  Rows: F w - f = 0 (F at f_density,
+    N(0, 0.1)), then the budget row sum(w) = 1.  0 <= w <= 0.01, f free.
+    c = -mu on w with mu ~ N(0.05, 0.02), 0 on f."""
+    rng = rng_for(FAM_PORTFOLIO, instance)
+    na, k = n_assets, k_factors
+    n = na + k
+    d = rng.uniform(0.01, 0.1, size=na)
+    Q = _csr(sp.diags(np.concatenate([d, np.ones(k)])))
+    F = _sparse_normal(rng, k, na, f_density, 0.1)
+    A = _csr(sp.vstack([sp.hstack([F, -sp.identity(k)]),
+                        sp.hstack([sp.csr_matrix(np.ones((1, na))), sp.csr_matrix((1, k))])]))
+    mu = rng.normal(0.05, 0.02, size=na)
+    c = np.concatenate([-mu, np.zeros(k)])
+    b = np.concatenate([np.zeros(k), [1.0]])
+    lb = np.concatenate([np.zeros(na), np.full(k, -np.inf)])
+    ub = np.concatenate([np.full(na, 0.01), np.full(k, np.inf)])
+    return QP(n=n, m=k + 1, Q=Q, A=A, c=c, b=b, sense=b"E" * (k + 1), lb=lb, ub=ub,
+              name=f"portfolio_n{na}_k{k}")
+
+
+# ---------------------------------------------------------------------------
+# small instances for pins and edge cases
+# ---------------------------------------------------------------------------
+
+def tiny(instance: int, n: int = 6, m: int = 3, density: float = 0.6,
+         q_rank: int | None = None, boxed: bool = True, senses: str = "EGL") -> QP:
+    """Tiny QP with a strictly convex Q = B^T B + 0.1 I (or rank-deficient
+    B^T B when q_rank is given), a random A, a box [-1, 1] when boxed, and
+    rows feasible at an interior point x0 ~ U(-0.5, 0.5)."""
+    rng = rng_for(FAM_TINY, instance)
+    r = n if q_rank is None else q_rank
+    B = rng.normal(size=(r, n))
+    Q = B.T @ B + (0.1 * np.eye(n) if q_rank is None else 0.0)
+    A = rng.normal(size=(m, n)) * (rng.uniform(size=(m, n)) < density)
+    for i in range(m):                     # no empty rows
+        if not A[i].any():
+            A[i, rng.integers(n)] = rng.normal()
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    sense = np.array([ord(senses[i % len(senses)]) for i in range(m)], dtype=np.uint8)
+    b = A @ x0
+    slack = rng.uniform(0.05, 0.3, size=m)
+    b = np.where(sense == ord("G"), b - slack, np.where(sense == ord("L"), b + slack, b))
+    c = rng.normal(size=n) * 2.0
+    lb = np.full(n, -1.0) if boxed else np.full(n, -np.inf)
+    ub = np.full(n, 1.0) if boxed else np.full(n, np.inf)
+    return QP(n=n, m=m, Q=_csr(Q), A=_csr(A), c=c, b=b, sense=sense.tobytes(),
+              lb=lb, ub=ub, name=f"tiny{instance}", meta={"x0": x0})
+
+
+def tiny_lp(instance: int, n: int = 8, m: int = 4) -> QP:
+    """Tiny bounded LP (Q = None): box [0, 2], rows feasible at x0 ~ U(0.5, 1.5)."""
+    rng = rng_for(FAM_LP, instance)
+    A = rng.normal(size=(m, n))
+    x0 = rng.uniform(0.5, 1.5, size=n)
+    sense = np.array([ord("EGL"[i % 3]) for i in range(m)], dtype=np.uint8)
+    b = A @ x0
+    b = np.where(sense == ord("G"), b - 0.2, np.where(sense == ord("L"), b + 0.2, b))
+    c = rng.normal(size=n)
+    return QP(n=n, m=m, Q=None, A=_csr(A), c=c, b=b, sense=sense.tobytes(),
+              lb=np.zeros(n), ub=np.full(n, 2.0), name=f"tiny_lp{instance}")
+
+
+def equality_qp(instance: int, n: int = 40, m: int = 15) -> QP:
+    """Unboxed, equality-only strictly convex QP (X = R^n, S = {b})."""
+    rng = rng_for(FAM_EQ, instance)
+    B = rng.normal(size=(n, n)) * (rng.uniform(size=(n, n)) < 0.2)
+    Q = B.T @ B / n + 0.5 * np.eye(n)
+    A = rng.normal(size=(m, n)) * (rng.uniform(size=(m, n)) < 0.3)
+    for i in range(m):
+        if not A[i].any():
+            A[i, rng.integers(n)] = 1.0
+    b = rng.normal(size=m)
+    c = rng.normal(size=n)
+    return QP(n=n, m=m, Q=_csr(Q), A=_csr(A), c=c, b=b, sense=b"E" * m,
+              lb=np.full(n, -np.inf), ub=np.full(n, np.inf), name=f"eq{instance}")
+
+
+def mixed_bounds(instance: int, n: int = 300, m: int = 120) -> QP:
+    """Medium sparse QP whose variables mix every bound kind: boxed, lower
+    only, upper only, free, and fixed (l = u); rows mix '=', '>=', '<='.
+    Feasible at x0 by construction."""
+    rng = rng_for(FAM_MIXED, instance)
+    B = _sparse_normal(rng, n // 2, n, 4.0 / n)
+    Q = _csr(B.T @ B + 0.05 * sp.identity(n))
+    A = _sparse_normal(rng, m, n, 6.0 / n).tolil()
+    for i in range(m):
+        if A.rows[i] == []:
+            A[i, int(rng.integers(n))] = 1.0
+    A = _csr(A)
+    kind = rng.integers(0, 5, size=n)
+    x0 = rng.uniform(-1.0, 1.0, size=n)
+    lb = np.where((kind == 0) | (kind == 1), x0 - rng.uniform(0.1, 1.0, n), -np.inf)
+    ub = np.where((kind == 0) | (kind == 2), x0 + rng.uniform(0.1, 1.0, n), np.inf)
+    lb = np.where(kind == 4, x0, lb)
+    ub = np.where(kind == 4, x0, ub)
+    sense = np.array([ord("EGL"[i % 3]) for i in range(m)], dtype=np.uint8)
+    b = A @ x0
+    b = np.where(sense == ord("G"), b - 0.1, np.where(sense == ord("L"), b + 0.1, b))
+    c = rng.normal(size=n)
+    return QP(n=n, m=m, Q=Q, A=A, c=c, b=b, sense=sense.tobytes(), lb=lb, ub=ub,
+              name=f"mixed{instance}")
+
+
+def unbounded_qp(instance: int = 0, n: int = 12, m: int = 5) -> QP:
+    """Dual-infeasible (unbounded) QP: variable 0 is free below, has zero
+    curvature (row/column 0 of Q is zero), zero column in A, and c_0 > 0,
+    so d = -e_0 is a ray with c^T d < 0, Q d = 0, A d = 0."""
+    rng = rng_for(FAM_TINY, 1000 + instance)
+    B = rng.normal(size=(n, n))
+    Q = B.T @ B / n + 0.2 * np.eye(n)
+    Q[0, :] = 0.0
+    Q[:, 0] = 0.0
+    A = rng.normal(size=(m, n))
+    A[:, 0] = 0.0
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    b = A @ x0
+    c = rng.normal(size=n)
+    c[0] = 1.0
+    lb = np.full(n, -1.0)
+    ub = np.full(n, 1.0)
+    lb[0] = -np.inf
+    ub[0] = 1.0
+    return QP(n=n, m=m, Q=_csr(Q), A=_csr(A), c=c, b=b, sense=b"E" * m, lb=lb, ub=ub,
+              name=f"unbounded{instance}")
+
+
+def contradictory_rows(instance: int = 0, n: int = 10, m: int = 4) -> QP:
+    """Primal-infeasible QP: rows 0 and 1 have the same coefficients and
+    right-hand sides b and b + 1 (both '='), so y = e_0 - e_1 (or its
+    negative) is a Farkas ray."""
+    q = tiny(2000 + instance, n=n, m=m, senses="E")
+    A = q.A.toarray()
+    A[1] = A[0]
+    b = q.b.copy()
+    b[1] = b[0] + 1.0
+    q.A = _csr(A)
+    q.b = b
+    q.name = f"contradictory{instance}"
+    return q
+
+
+def box_infeasible_rows(instance: int = 0, n: int = 8, m: int = 3) -> QP:
+    """Primal-infeasible through the box: row 0 asks sum(x) >= n + 1 while
+    every x_i <= 1."""
+    q = tiny(3000 + instance, n=n, m=m, senses="E")
+    A = q.A.toarray()
+    A[0] = 1.0
+    b = q.b.copy()
+    b[0] = n + 1.0
+    s = bytearray(q.sense)
+    s[0] = ord("G")
+    q.A = _csr(A)
+    q.b = b
+    q.sense = bytes(s)
+    q.name = f"box_infeasible{instance}"
+    return q
