@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark: QPs solved per second at 1e-6 relative KKT on one MI355X.
+
+One step is one full solve (every outer PDHG iteration and every inner
+conjugate-gradient iteration, on device) of the large sparse workload:
+n = 1e6 variables, m = 5e5 rows (half '=', half '>='), Q symmetric with
+about 10 random off-diagonals per row and a dominant diagonal, A with 8
+nonzeros per row, box [0, 10], tolerance 1e-6.  The problem data is
+resident in HBM before the timed region (qp_create runs first).
+
+Prints one JSON line with the throughput, p50/p99 latency, the roofline
+of the dominant kernel (measured with HIP events inside the timed solves)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QPs solved/s at 1e-6 rel KKT + achieved HBM GB/s; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_hp_large_sparse.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernels_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pdhcg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_23967_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def hp_bytes(n, nnz_q):
+    """Algorithmic HBM bytes of one launch of the inner H p kernel:
+    CSR values and columns (12 B per nonzero), int32 row pointers, the
+    gathered operand p once, the epilogue reads g, x, l_v, u_v and the
+    write of Hp (8 B each per row)."""
+    return 12 * nnz_q + 4 * (n + 1) + 8 * n * 6
+
+
+def cpu_baseline(q, gpu_units_per_solve, sample_iters):
+    """The oracle on the host cores: setup alone (max_iter = 0), then the
+    first `sample_iters` outer iterations; the per-iteration cost (outer
+    plus inner iterations counted as equal units) is scaled to one full
+    solve with the GPU's unit count (setup excluded on both sides)."""
+    import oracle
+
+    t = time.perf_counter()
+    oracle.solve(q, max_iter=0)
+    t0 = time.perf_counter() - t
+    log(f"oracle setup {t0:.1f}s")
+    t = time.perf_counter()
+    r = oracle.solve(q, max_iter=sample_iters)
+    t1 = time.perf_counter() - t
+    units = r.info["iterations"] + r.info["inner_iterations"]
+    per_unit = max(t1 - t0, 1e-9) / max(units, 1)
+    est = per_unit * gpu_units_per_solve
+    log(f"oracle sample {t1:.1f}s, {r.info['iterations']} outer + {r.info['inner_iterations']} inner")
+    return {
+        "value": 1.0 / est,
+        "unit": "QPs solved/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle_qp_solve on the same instance for the first {sample_iters} outer "
+                   f"iterations ({r.info['iterations']} outer + {r.info['inner_iterations']} inner "
+                   f"in {t1 - t0:.2f}s beyond its {t0:.2f}s setup); per-iteration time scaled to "
+                   f"the GPU run's {gpu_units_per_solve} outer+inner iterations per solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--timing", type=int, default=4, help="time every k-th launch per kernel family")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2602_23967_amd as P
+    from paper_2602_23967_amd import instances as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    t = time.perf_counter()
+    q = I.large_sparse(0, n=args.n)
+    log(f"generated {q.name}: n={q.n} m={q.m} nnz(Q)={q.nnz_Q} nnz(A)={q.nnz_A} "
+        f"in {time.perf_counter() - t:.1f}s")
+    h = P.qp_create_from(q)
+    params = P.qp_params_default(tol=args.tol, timing=args.timing)
+    try:
+        for w in range(args.warmup):
+            st = P.qp_solve_ex(h, params)
+            log(f"warmup {w}: {P.STATUS_NAMES[st]}")
+        torch.cuda.synchronize()
+        lat, infos = [], []
+        t_start = time.perf_counter()
+        for s in range(args.steps):
+            a = time.perf_counter()
+            st = P.qp_solve_ex(h, params)
+            lat.append(time.perf_counter() - a)
+            _, x, y, info = P.qp_result(h, q.n, q.m)
+            infos.append(info)
+            log(f"step {s}: {P.STATUS_NAMES[st]} {lat[-1]:.3f}s it={info['iterations']} "
+                f"inner={info['inner_iterations']} kkt=({info['r_primal']:.1e},{info['r_dual']:.1e},"
+                f"{info['r_gap']:.1e})")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+    finally:
+        _, x, y, info = P.qp_result(h, q.n, q.m)
+        P.qp_destroy(h)
+
+    solved = all(i["status"] == P.OPTIMAL and max(i["r_primal"], i["r_dual"], i["r_gap"]) <= args.tol
+                 for i in infos)
+    # the dominant kernel: the fused inner H p product
+    f = P.FAMILIES.index("spmv_hp")
+    timed = sum(i["fam_timed"][f] for i in infos)
+    ms = sum(i["fam_ms"][f] for i in infos)
+    avg_us = 1e3 * ms / max(timed, 1)
+    nbytes = hp_bytes(q.n, q.nnz_Q)
+    achieved = nbytes / (avg_us * 1e-6) / 1e9 if timed else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernels_digest") == kernels_digest():
+            traffic = tr.get("bytes_per_launch")
+    kern = {}
+    for j, name in enumerate(P.FAMILIES):
+        tj = sum(i["fam_timed"][j] for i in infos)
+        if tj:
+            kern[name] = {"avg_us": round(1e3 * sum(i["fam_ms"][j] for i in infos) / tj, 3),
+                          "launches_per_solve": infos[-1]["fam_launches"][j]}
+    units = infos[-1]["iterations"] + infos[-1]["inner_iterations"]
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "QPs solved/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"large sparse convex QP n={q.n} m={q.m} (half '=', half '>='), "
+                               f"Q SPD ~10 off-diagonals/row, A 8 nnz/row, box [0,10], tol {args.tol:g}",
+                   "n": q.n, "m": q.m, "nnz_Q": q.nnz_Q, "nnz_A": q.nnz_A, "tol": args.tol},
+        "solved": solved,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "iterations": {"outer": infos[-1]["iterations"], "inner": infos[-1]["inner_iterations"],
+                       "outer_per_s": infos[-1]["iterations"] / np.median(lat),
+                       "inner_per_s": infos[-1]["inner_iterations"] / np.median(lat)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "kernel": "k_spmv<EpiStepA> (inner H p)", "bytes_per_launch": nbytes,
+                     "avg_us": avg_us, "timed_launches": timed},
+        "kernels": kern,
+        "setup_s": info["setup_seconds"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(q, units, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

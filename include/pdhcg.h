@@ -1,0 +1,218 @@
+/*
+ * pdhcg.h -- C ABI of the MI355X (gfx950) PDHCG-II convex-QP solver.
+ *
+ * Problem (Section 2, eq. QP, of arXiv 2602.23967):
+ *
+ *     minimize    1/2 x'Qx + c'x
+ *     subject to  l_c <= A x <= u_c       (rows; here from b and a sense)
+ *                 l_v <=  x  <= u_v       (box; bounds may be +-INFINITY)
+ *
+ * with Q symmetric positive semidefinite.  The solver is the restarted,
+ * reflected-Halpern PDHG iteration of Sections 2.1 and 3 with the primal
+ * subproblem solved by conjugate gradients on the free set (closed form
+ * when Q is diagonal), the PID primal weight of Section 3.2, the adaptive
+ * inner tolerance of Section 3.3, the relative L-infinity KKT test of
+ * Section 4 and the infeasibility certificates of Section 5.  All arithmetic
+ * is IEEE FP64.
+ *
+ * Conventions (Section 2, eq. dualQP / minimax): y_i > 0 means the row's
+ * upper bound is active, y_i < 0 its lower bound; '>=' rows therefore have
+ * y_i <= 0.  The reduced cost is r = Qx + c + A'y.
+ *
+ * Ownership and threading: qp_create copies every input (the caller may free
+ * its buffers on return); the handle owns all device memory until
+ * qp_destroy.  One thread at a time per handle.  Distinct handles on
+ * distinct streams may run concurrently.  Pointers documented as "device"
+ * are HIP device pointers (e.g. torch.cuda tensors' data_ptr()); all others
+ * are host pointers.
+ *
+ * Errors: functions returning int give a status (>= 0) or a negative error
+ * code; qp_last_error() then describes the failure (thread-local string).
+ */
+#ifndef PDHCG_H
+#define PDHCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qp_handle qp_handle;
+
+/* solve status (>= 0) */
+enum {
+    QP_NOT_SOLVED = 0,
+    QP_OPTIMAL = 1,            /* max(r_primal, r_dual, r_gap) <= tol (Section 4) */
+    QP_PRIMAL_INFEASIBLE = 2,  /* Farkas ray found (Section 5.1); y holds it */
+    QP_DUAL_INFEASIBLE = 3,    /* unbounded ray found (Section 5.2); x holds it */
+    QP_ITERATION_LIMIT = 4,
+    QP_NUMERICAL_ERROR = 5     /* a residual became NaN or infinite */
+};
+
+/* error codes (< 0) */
+enum {
+    QP_ERR_INVALID_ARG = -1,   /* malformed input; nothing was allocated */
+    QP_ERR_NOT_SYMMETRIC = -2, /* Q is not symmetric (pattern or values) */
+    QP_ERR_DEVICE = -3,        /* HIP error or out of device memory */
+    QP_ERR_STATE = -4          /* e.g. qp_result before any qp_solve */
+};
+
+/* operators for qp_apply */
+enum { QP_OP_Q = 0, QP_OP_A = 1, QP_OP_AT = 2 };
+
+/* Solver parameters.  Fields marked (paper) are values the paper states;
+ * the others are readings where the paper is silent. */
+typedef struct {
+    double tol;               /* (paper, Section 4) eps_tol on max(r_primal, r_dual, r_gap); 1e-6 */
+    int64_t max_iter;         /* outer PDHG iterations; 0 returns the start point's residuals */
+    int64_t check_every;      /* cadence of KKT / infeasibility / restart checks; 64 */
+    int64_t max_inner;        /* cap on inner iterations per subproblem; 500 */
+    int use_halpern;          /* 1: reflected Halpern averaging (Section 3.1); 0: plain PDHG */
+    int inner_lag;            /* inner steps queued ahead of the host's view of the stop flag; 2 */
+    double theta;             /* Halpern reflection; 1 */
+    double kp, ki, kd;        /* PID gains on log(omega) (Section 3.2); 0.99, 0.01, 0 */
+    double gamma_inner;       /* (paper, Section 3.3) 5e-4 */
+    double eps_min;           /* (paper, Section 3.3) 1e-9 */
+    double eps_inner_fixed;   /* > 0: fixed inner tolerance instead of the adaptive rule; 0 */
+    double restart_sufficient, restart_necessary, restart_artificial; /* 0.2, 0.8, 0.36 */
+    double eps_inf;           /* certificate tolerance (Section 5); 1e-8 */
+    double eta_scale;         /* (paper, Section 3.2) eta = eta_scale / ||A||_2; 0.998 */
+    double norm_safety;       /* ||A||_2 estimate multiplied by this; 1.01 */
+    double power_tol;         /* power-iteration relative-change tolerance; 1e-7 */
+    int64_t power_max_iter;   /* 1000 */
+    double mprgp_gamma;       /* proportioning constant of the inner solver; 1 */
+    double mprgp_abar_scale;  /* expansion step = scale / (||Q||_2 + 1/tau); 1.9 */
+    int timing;               /* > 0: time every `timing`-th launch of each kernel family */
+    int reserved;
+} qp_params;
+
+/* kernel families reported by qp_info.fam_* when timing is on */
+enum {
+    QP_FAM_SPMV_HP = 0,   /* inner step: H p (or H x after an expansion), fused */
+    QP_FAM_UPDATE = 1,    /* inner step: x, g update with reductions */
+    QP_FAM_DIR = 2,       /* inner step: next direction */
+    QP_FAM_RHS = 3,       /* A'y fused with the subproblem right-hand side (or closed form) */
+    QP_FAM_GINIT = 4,     /* gradient at the warm start */
+    QP_FAM_DUAL = 5,      /* A x_bar fused with the dual step and Halpern on y */
+    QP_FAM_HALPX = 6,     /* Halpern on x, movement norms, tolerance update */
+    QP_FAM_CHECK = 7,     /* KKT / infeasibility / restart checks */
+    QP_NFAM = 8
+};
+
+typedef struct {
+    int status;
+    int reserved;
+    int64_t iterations;        /* outer iterations */
+    int64_t inner_iterations;  /* total inner (CG/MPRGP) iterations */
+    int64_t restarts;
+    int64_t checks;
+    double r_primal, r_dual, r_gap;  /* Section 4, at the returned point */
+    double primal_obj, dual_obj;
+    double natural_residual;   /* ||x - proj_X(x - r)||_inf (diagnostic) */
+    double omega, eta, norm_A, norm_Q, eps_inner;
+    double solve_seconds;      /* wall time of the last qp_solve */
+    double setup_seconds;      /* wall time of qp_create */
+    double fam_ms[QP_NFAM];    /* summed device time of the timed launches */
+    int64_t fam_timed[QP_NFAM];/* number of timed launches */
+    int64_t fam_launches[QP_NFAM]; /* number of launches */
+} qp_info;
+
+/* Defaults listed above. */
+qp_params qp_params_default(void);
+
+/*
+ * Create a problem.  Q is full symmetric CSR (both triangles; int64 row
+ * pointers of length n+1, int32 column indices sorted and unique within a
+ * row); Q_rowptr == NULL means Q = 0 (an LP).  A is m x n CSR in the same
+ * form (may be NULL when m == 0).  sense[i] is 'E' (A_i x = b_i), 'G'
+ * (A_i x >= b_i) or 'L' (A_i x <= b_i), mapped to (l_c, u_c) as in Section 2.
+ * lb / ub may be NULL (-inf / +inf).  Validation (before any device call):
+ * n >= 1, m >= 0, row pointers start at 0 and do not decrease, nnz < 2^31,
+ * columns in range, sorted and unique, every value, c and b finite, lb <= ub,
+ * lb < +inf, ub > -inf, Q symmetric to 1e-14 relative.  Returns 0 and
+ * *out, or a negative error code (nothing allocated).
+ */
+int qp_create(int64_t n, int64_t m,
+              const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
+              const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+              const double* c, const double* b, const char* sense,
+              const double* lb, const double* ub, qp_handle** out);
+
+/* Same with the row bounds given directly: l_c <= A x <= u_c (Section 2,
+ * eq. QP); lc / uc may hold -inf / +inf and must satisfy lc <= uc. */
+int qp_create_ranged(int64_t n, int64_t m,
+                     const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
+                     const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+                     const double* c, const double* lc, const double* uc,
+                     const double* lb, const double* ub, qp_handle** out);
+
+/* Run every later call of this handle on `stream` (a hipStream_t; NULL
+ * selects the handle's own stream).  The caller keeps ownership. */
+int qp_set_stream(qp_handle* h, void* stream);
+
+/* Solve from the start point x0 = proj_X(0), y0 = 0 with default
+ * parameters except tol and max_iter.  Blocking.  Returns the status. */
+int qp_solve(qp_handle* h, double tol, int64_t max_iter);
+
+/* Solve with explicit parameters (NULL: defaults). */
+int qp_solve_ex(qp_handle* h, const qp_params* params);
+
+/*
+ * Copy the last solve's result into caller buffers (host; any may be NULL):
+ * x (n), y (m), info.  OPTIMAL / ITERATION_LIMIT / NUMERICAL_ERROR: the
+ * PDHG output (x_T, y_T) of the last iteration, x in X and y in Y.
+ * PRIMAL_INFEASIBLE: y = the Farkas ray, ||y||_inf = 1 (x = x_T).
+ * DUAL_INFEASIBLE: x = the unbounded direction, ||x||_inf = 1 (y = y_T).
+ * Returns the status, or QP_ERR_STATE before the first solve.
+ */
+int qp_result(const qp_handle* h, double* x, double* y, qp_info* info);
+
+/* Release all device memory of the handle.  NULL is ignored. */
+void qp_destroy(qp_handle* h);
+
+/* Description of the last error on this thread ("" if none). */
+const char* qp_last_error(void);
+
+/* ---- operator-level calls on caller-owned DEVICE buffers -----------------
+ * They run the same kernels the solver runs, synchronously on the handle's
+ * stream, and exist so each step can be checked in isolation. */
+
+/* y = M x for M in {Q (n x n), A (m x n), A' (n x m)} (device x, y). */
+int qp_apply(qp_handle* h, int op, const double* x, double* y);
+
+/* *out (host) = a'b over len elements (device a, b), deterministic. */
+int qp_dot(qp_handle* h, int64_t len, const double* a, const double* b, double* out);
+
+/* One primal subproblem (Section 2.2, eq. primal_update):
+ *   x <- argmin over l_v <= x <= u_v of 1/2 x'(Q + I/tau)x - rhs'x,
+ * started from x (device, n; clipped to the box first), stopping when the
+ * projected-gradient 2-norm is <= eps or after max_inner iterations.
+ * iters and res (host, may be NULL) receive the iteration count and the
+ * final projected-gradient norm. */
+int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double eps,
+                  int64_t max_inner, int64_t* iters, double* res);
+
+/* KKT residuals of Section 4 at (x, y) (device, n and m).  out (host, 7):
+ * r_primal, r_dual, r_gap, primal objective, dual objective, natural
+ * residual, unnormalised primal violation. */
+int qp_kkt(qp_handle* h, const double* x, const double* y, double* out);
+
+/* ||A||_2 and ||Q||_2 estimates of qp_create (host outputs, may be NULL). */
+int qp_norms(const qp_handle* h, double* norm_A, double* norm_Q);
+
+/* ---- host-only diagnostics (no device call) --------------------------- */
+
+/* The SpMV work schedule the library builds for a CSR with `rows` rows and
+ * int64 row pointers `rowptr` (host): row blocks of at most 2048 nonzeros
+ * and 256 rows, and 2048-nonzero segments of longer rows.  Writes up to
+ * `cap` items of 8 int32 each to `out` (host; may be NULL to count):
+ * {first row, rows (0 for a segment), first nonzero, end nonzero,
+ *  long-row id, segment index, segment count, first segment slot}.
+ * Returns the number of items (or a negative error code). */
+int64_t qp_spmv_schedule(int64_t rows, const int64_t* rowptr, int32_t* out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

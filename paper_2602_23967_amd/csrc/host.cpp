@@ -1,0 +1,887 @@
+// host.cpp -- C ABI of the gfx950 PDHCG-II solver: input validation, device
+// setup (transpose, SpMV schedules, norm estimates) and the host side of the
+// solve loop.  All arithmetic of the method runs in kernels.hip; the host
+// only enqueues kernels, watches a pinned status word the kernels post, and
+// copies results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pdhcg.h"
+#include "pdhcg_internal.h"
+
+using namespace pdhcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// validation (host only, runs before any device call)
+// ---------------------------------------------------------------------------
+
+int check_csr(const char* name, int64_t rows, int64_t cols, const int64_t* rp, const int32_t* cj,
+              const double* v)
+{
+    if (!rp) return fail(QP_ERR_INVALID_ARG, std::string(name) + ": row pointer is NULL");
+    if (rp[0] != 0) return fail(QP_ERR_INVALID_ARG, std::string(name) + ": rowptr[0] != 0");
+    for (int64_t i = 0; i < rows; ++i)
+        if (rp[i + 1] < rp[i])
+            return fail(QP_ERR_INVALID_ARG, std::string(name) + ": row pointers decrease at row " +
+                                                std::to_string(i));
+    const int64_t nnz = rp[rows];
+    if (nnz >= (int64_t)INT32_MAX)
+        return fail(QP_ERR_INVALID_ARG, std::string(name) + ": nnz must be below 2^31");
+    if (nnz > 0 && (!cj || !v))
+        return fail(QP_ERR_INVALID_ARG, std::string(name) + ": column or value array is NULL");
+    for (int64_t i = 0; i < rows; ++i) {
+        int64_t prev = -1;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = cj[k];
+            if (j < 0 || j >= cols)
+                return fail(QP_ERR_INVALID_ARG, std::string(name) + ": column out of range in row " +
+                                                    std::to_string(i));
+            if (j <= prev)
+                return fail(QP_ERR_INVALID_ARG, std::string(name) +
+                                                    ": columns not sorted or duplicated in row " +
+                                                    std::to_string(i));
+            if (!std::isfinite(v[k]))
+                return fail(QP_ERR_INVALID_ARG, std::string(name) + ": non-finite value in row " +
+                                                    std::to_string(i));
+            prev = j;
+        }
+    }
+    return 0;
+}
+
+// transpose of an (rows x cols) CSR by counting sort (columns stay sorted)
+void transpose(int64_t rows, int64_t cols, const int64_t* rp, const int32_t* cj, const double* v,
+               std::vector<int64_t>& tp, std::vector<int32_t>& tj, std::vector<double>& tv)
+{
+    const int64_t nnz = rp[rows];
+    tp.assign(cols + 1, 0);
+    tj.resize(nnz);
+    tv.resize(nnz);
+    for (int64_t k = 0; k < nnz; ++k) tp[cj[k] + 1]++;
+    for (int64_t j = 0; j < cols; ++j) tp[j + 1] += tp[j];
+    std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t d = fill[cj[k]]++;
+            tj[d] = (int32_t)i;
+            tv[d] = v[k];
+        }
+}
+
+int check_symmetric(int64_t n, const int64_t* rp, const int32_t* cj, const double* v)
+{
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tj;
+    std::vector<double> tv;
+    transpose(n, n, rp, cj, v, tp, tj, tv);
+    for (int64_t i = 0; i <= n; ++i)
+        if (tp[i] != rp[i]) return fail(QP_ERR_NOT_SYMMETRIC, "Q: sparsity pattern is not symmetric");
+    for (int64_t k = 0; k < rp[n]; ++k) {
+        if (tj[k] != cj[k]) return fail(QP_ERR_NOT_SYMMETRIC, "Q: sparsity pattern is not symmetric");
+        const double a = v[k], b = tv[k];
+        if (std::fabs(a - b) > 1e-14 * std::max(std::fabs(a), std::fabs(b)))
+            return fail(QP_ERR_NOT_SYMMETRIC, "Q: values are not symmetric");
+    }
+    return 0;
+}
+
+int check_vec(const char* name, int64_t len, const double* v, bool allow_inf)
+{
+    if (!v) return fail(QP_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    for (int64_t i = 0; i < len; ++i) {
+        if (std::isnan(v[i]) || (!allow_inf && !std::isfinite(v[i])))
+            return fail(QP_ERR_INVALID_ARG, std::string(name) + ": invalid entry " + std::to_string(i));
+    }
+    return 0;
+}
+
+int check_bounds(const char* name, int64_t len, const double* l, const double* u)
+{
+    for (int64_t i = 0; i < len; ++i) {
+        if (std::isnan(l[i]) || std::isnan(u[i]) || l[i] > u[i] || l[i] == INFINITY || u[i] == -INFINITY)
+            return fail(QP_ERR_INVALID_ARG, std::string(name) + ": invalid bounds at " + std::to_string(i));
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// SpMV schedule: greedy row blocks of <= NNZ_CAP nonzeros and <= ROWS_CAP
+// rows; a row longer than NNZ_CAP becomes NNZ_CAP-sized segments
+// ---------------------------------------------------------------------------
+
+void build_plan(int64_t rows, const int64_t* rp, std::vector<BlkDesc>& blk, int& nlr, int& nseg_tot)
+{
+    blk.clear();
+    nlr = 0;
+    nseg_tot = 0;
+    int64_t r = 0;
+    while (r < rows) {
+        const int64_t L = rp[r + 1] - rp[r];
+        if (L > NNZ_CAP) {
+            const int nseg = (int)((L + NNZ_CAP - 1) / NNZ_CAP);
+            for (int s = 0; s < nseg; ++s) {
+                const int64_t a = rp[r] + (int64_t)s * NNZ_CAP;
+                const int64_t b = std::min(a + (int64_t)NNZ_CAP, rp[r + 1]);
+                blk.push_back({(int)r, 0, (int)a, (int)b, nlr, s, nseg, nseg_tot});
+            }
+            ++nlr;
+            nseg_tot += nseg;
+            ++r;
+            continue;
+        }
+        const int64_t start = r;
+        int64_t nnz = 0;
+        while (r < rows && r - start < ROWS_CAP) {
+            const int64_t Lr = rp[r + 1] - rp[r];
+            if (Lr > NNZ_CAP || nnz + Lr > NNZ_CAP) break;
+            nnz += Lr;
+            ++r;
+        }
+        blk.push_back({(int)start, (int)(r - start), (int)rp[start], (int)rp[r], 0, 0, 0, 0});
+    }
+    if (blk.empty()) blk.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+}
+
+struct EventPair {
+    hipEvent_t a, b;
+    int fam;
+};
+
+}  // namespace
+
+struct qp_handle {
+    int64_t n = 0, m = 0;
+    DevState S;
+    hipStream_t own = nullptr, stream = nullptr;
+    unsigned long long* hstat = nullptr;
+    unsigned long long* hcheck = nullptr;
+    std::vector<void*> dev_allocs;
+    int solved = 0;
+    int status = QP_NOT_SOLVED;
+    qp_info info{};
+    double norm_A = 0.0, norm_Q_raw = 0.0, norm_Q = 0.0, omega0 = 1.0;
+    double c_max = 0.0, bscale_p = 1.0, gamma_q = 1.0;
+    int has_unbounded_x = 0;
+    int qkind = 0;   // 0 none, 1 diagonal, 2 general
+    double setup_seconds = 0.0;
+    // timing
+    std::vector<EventPair> ev_pool;
+    size_t ev_used = 0;
+    int timing = 0;
+    int64_t fam_launches[QP_NFAM] = {};
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(QP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+template <class T>
+int dalloc(qp_handle* h, T** p, size_t count)
+{
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    h->dev_allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return 0;
+}
+
+template <class T>
+int upload(qp_handle* h, T** p, const T* src, size_t count)
+{
+    int rc = dalloc(h, p, count);
+    if (rc) return rc;
+    if (count) HIPCHK(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_t* rp,
+               const int32_t* cj, const double* v)
+{
+    M.rows = (int)rows;
+    M.cols = (int)cols;
+    M.nnz = rp ? rp[rows] : 0;
+    std::vector<int> rp32(rows + 1, 0);
+    for (int64_t i = 0; i <= rows; ++i) rp32[i] = rp ? (int)rp[i] : 0;
+    int rc;
+    if ((rc = upload(h, &M.rowptr, rp32.data(), rows + 1))) return rc;
+    if ((rc = upload(h, &M.col, cj, (size_t)M.nnz))) return rc;
+    if ((rc = upload(h, &M.val, v, (size_t)M.nnz))) return rc;
+    std::vector<int64_t> rp64(rows + 1, 0);
+    if (rp) std::copy(rp, rp + rows + 1, rp64.begin());
+    std::vector<BlkDesc> blk;
+    int nlr = 0, nseg = 0;
+    build_plan(rows, rp64.data(), blk, nlr, nseg);
+    M.nblk = (int)blk.size();
+    if ((rc = upload(h, &M.blk, blk.data(), blk.size()))) return rc;
+    if ((rc = dalloc(h, &M.seg_part, (size_t)std::max(nseg, 1)))) return rc;
+    if ((rc = dalloc(h, &M.lr_count, (size_t)std::max(nlr, 1)))) return rc;
+    HIPCHK(hipMemset(M.lr_count, 0, sizeof(unsigned) * std::max(nlr, 1)));
+    return 0;
+}
+
+hipStream_t stream_of(const qp_handle* h) { return h->stream; }
+
+// power-iteration estimate of ||M||_2 through M'M (Mt = M' as a CSR),
+// the same sequence as the oracle: w = M v, sigma = ||w||, u = M' w,
+// v = u / ||u||, stop when sigma changes by <= tol * sigma
+int power_norm(qp_handle* h, const CsrDev& M, const CsrDev& Mt, double tol, int64_t max_iter,
+               double* out)
+{
+    *out = 0.0;
+    if (M.rows == 0 || M.cols == 0 || M.nnz == 0) return 0;
+    DevState& S = h->S;
+    hipStream_t s = stream_of(h);
+    double* v = S.v1;
+    double* w = S.v2;
+    HIPCHK(launch_power_start(S, v, M.cols, s));
+    HIPCHK(launch_scale(S, v, M.cols, s));
+    double sig = 0.0, prev = 0.0;
+    for (int64_t it = 1; it <= max_iter; ++it) {
+        HIPCHK(launch_spmv_norm(S, M, v, w, s));
+        HIPCHK(hipMemcpyAsync(&h->hcheck[1], &S.ctrl->pw_norm, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(launch_spmv_norm(S, Mt, w, v, s));
+        HIPCHK(hipMemcpyAsync(&h->hcheck[2], &S.ctrl->pw_norm, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(launch_scale(S, v, M.cols, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double nu;
+        std::memcpy(&sig, &h->hcheck[1], sizeof(double));
+        std::memcpy(&nu, &h->hcheck[2], sizeof(double));
+        if (sig == 0.0 || nu == 0.0) break;
+        if (std::fabs(sig - prev) <= tol * sig) break;
+        prev = sig;
+    }
+    *out = sig;
+    return 0;
+}
+
+int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, const double* Qv,
+                const int64_t* Ap, const int32_t* Aj, const double* Av, const double* c,
+                const double* lc, const double* uc, const double* lb, const double* ub,
+                qp_handle** out)
+{
+    const double t0 = now_s();
+    int rc;
+    std::vector<double> lvv(n), uvv(n);
+    for (int64_t i = 0; i < n; ++i) {
+        lvv[i] = lb ? lb[i] : -INFINITY;
+        uvv[i] = ub ? ub[i] : INFINITY;
+    }
+    if ((rc = check_bounds("lb/ub", n, lvv.data(), uvv.data()))) return rc;
+    if ((rc = check_vec("c", n, c, false))) return rc;
+    std::vector<int64_t> a_empty(1, 0);
+    if (!Ap) {
+        if (m != 0) return fail(QP_ERR_INVALID_ARG, "A: row pointer is NULL");
+        Ap = a_empty.data();
+    }
+    if ((rc = check_csr("A", m, n, Ap, Aj, Av))) return rc;
+    if (Qp) {
+        if ((rc = check_csr("Q", n, n, Qp, Qj, Qv))) return rc;
+        if ((rc = check_symmetric(n, Qp, Qj, Qv))) return rc;
+    }
+
+    // ---- device setup -------------------------------------------------------
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(QP_ERR_DEVICE, "no HIP device available");
+
+    qp_handle* h = new qp_handle();
+    h->n = n;
+    h->m = m;
+    DevState& S = h->S;
+    S.n = (int)n;
+    S.m = (int)m;
+    auto bail = [&](int code) {
+        qp_destroy(h);
+        return code;
+    };
+    if (hipStreamCreate(&h->own) != hipSuccess) return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    h->stream = h->own;
+    if (hipHostMalloc((void**)&h->hstat, 4 * sizeof(unsigned long long),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipHostMalloc failed"));
+    h->hcheck = h->hstat + 1;
+    std::memset(h->hstat, 0, 4 * sizeof(unsigned long long));
+    if (hipHostGetDevicePointer((void**)&S.dstat, h->hstat, 0) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipHostGetDevicePointer failed"));
+    S.dcheck = S.dstat + 1;
+
+    // Q kind: none, diagonal (closed-form primal step) or general
+    std::vector<double> qd(n, 0.0);
+    h->qkind = 0;
+    if (Qp) {
+        h->qkind = 1;
+        for (int64_t i = 0; i < n && h->qkind == 1; ++i)
+            for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k)
+                if (Qj[k] != i) { h->qkind = 2; break; }
+        if (h->qkind == 1)
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) qd[i] += Qv[k];
+    }
+    S.qdiag = h->qkind < 2;
+
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tj;
+    std::vector<double> tv;
+    transpose(m, n, Ap, Aj, Av, tp, tj, tv);
+    if ((rc = upload_csr(h, S.A, m, n, Ap, Aj, Av))) return bail(rc);
+    if ((rc = upload_csr(h, S.AT, n, m, tp.data(), tj.data(), tv.data()))) return bail(rc);
+    std::vector<int64_t> q_empty(n + 1, 0);
+    if ((rc = upload_csr(h, S.Q, n, n, Qp ? Qp : q_empty.data(), Qj, Qv))) return bail(rc);
+
+    std::vector<double> lcv(m), ucv(m);
+    for (int64_t i = 0; i < m; ++i) { lcv[i] = lc[i]; ucv[i] = uc[i]; }
+    if ((rc = upload(h, &S.qd, qd.data(), n))) return bail(rc);
+    if ((rc = upload(h, &S.c, c, n))) return bail(rc);
+    if ((rc = upload(h, &S.lv, lvv.data(), n))) return bail(rc);
+    if ((rc = upload(h, &S.uv, uvv.data(), n))) return bail(rc);
+    if ((rc = upload(h, &S.lc, lcv.data(), m))) return bail(rc);
+    if ((rc = upload(h, &S.uc, ucv.data(), m))) return bail(rc);
+    double** nvecs[] = {&S.x, &S.xa, &S.xt, &S.rhs, &S.g, &S.p, &S.hp, &S.aty, &S.dx};
+    for (double** pv : nvecs)
+        if ((rc = dalloc(h, pv, n))) return bail(rc);
+    double** mvecs[] = {&S.y, &S.ya, &S.yt, &S.ytil};
+    for (double** pv : mvecs)
+        if ((rc = dalloc(h, pv, m))) return bail(rc);
+    const int64_t nm = std::max(n, m);
+    if ((rc = dalloc(h, &S.v1, nm))) return bail(rc);
+    if ((rc = dalloc(h, &S.v2, nm))) return bail(rc);
+    if ((rc = dalloc(h, &S.ctrl, 1))) return bail(rc);
+    const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, VEC_GRID_MAX});
+    if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8))) return bail(rc);
+    if ((rc = dalloc(h, &S.counter, 1))) return bail(rc);
+    if (hipMemset(S.counter, 0, sizeof(unsigned)) != hipSuccess ||
+        hipMemset(S.ctrl, 0, sizeof(Ctrl)) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipMemset failed"));
+
+    // scalars of the problem
+    qp_params d = qp_params_default();
+    if ((rc = power_norm(h, S.A, S.AT, d.power_tol, d.power_max_iter, &h->norm_A))) return bail(rc);
+    if (h->qkind == 2) {
+        if ((rc = power_norm(h, S.Q, S.Q, d.power_tol, d.power_max_iter, &h->norm_Q_raw))) return bail(rc);
+        h->norm_Q = d.norm_safety * h->norm_Q_raw;
+    } else {
+        h->norm_Q = 0.0;
+        for (int64_t i = 0; i < n; ++i) h->norm_Q = std::max(h->norm_Q, std::fabs(qd[i]));
+    }
+    double nb = 0.0, nc = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        const double bt = std::isfinite(lc[i]) ? lc[i] : (std::isfinite(uc[i]) ? uc[i] : 0.0);
+        nb += bt * bt;
+    }
+    for (int64_t i = 0; i < n; ++i) nc += c[i] * c[i];
+    nb = std::sqrt(nb);
+    nc = std::sqrt(nc);
+    h->omega0 = (nc > 1e-10 && nb > 1e-10) ? nc / nb : 1.0;
+    h->c_max = 0.0;
+    for (int64_t i = 0; i < n; ++i) h->c_max = std::max(h->c_max, std::fabs(c[i]));
+    double bl = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (std::isfinite(lc[i])) bl = std::max(bl, std::fabs(lc[i]));
+        if (std::isfinite(uc[i])) bl = std::max(bl, std::fabs(uc[i]));
+    }
+    h->bscale_p = 1.0 + bl;
+    h->gamma_q = 1.0;
+    if (Qp)
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) s += std::fabs(Qv[k]);
+            h->gamma_q = std::max(h->gamma_q, s);
+        }
+    h->has_unbounded_x = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(lvv[i]) || !std::isfinite(uvv[i])) h->has_unbounded_x = 1;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(QP_ERR_DEVICE, "setup failed"));
+    h->setup_seconds = now_s() - t0;
+    *out = h;
+    g_err.clear();
+    return 0;
+}
+
+// ---- timing of kernel families ----------------------------------------------
+
+struct Timed {
+    qp_handle* h;
+    int fam;
+    EventPair* ev = nullptr;
+    Timed(qp_handle* hh, int f) : h(hh), fam(f)
+    {
+        const int64_t k = h->fam_launches[fam]++;
+        if (h->timing > 0 && k % h->timing == 0 && h->ev_used < h->ev_pool.size()) {
+            ev = &h->ev_pool[h->ev_used++];
+            ev->fam = fam;
+            (void)hipEventRecord(ev->a, h->stream);
+        }
+    }
+    ~Timed()
+    {
+        if (ev) (void)hipEventRecord(ev->b, h->stream);
+    }
+};
+
+void setup_ctrl(qp_handle* h, const qp_params& p, Ctrl& c)
+{
+    std::memset(&c, 0, sizeof(c));
+    c.omega0 = h->omega0;
+    c.omega = h->omega0;
+    c.norm_A = h->norm_A;
+    c.eta = h->norm_A * p.norm_safety > 1e-12 ? p.eta_scale / (p.norm_safety * h->norm_A) : 1.0;
+    c.tau = c.eta / c.omega;
+    c.sigma = c.eta * c.omega;
+    c.inv_tau = 1.0 / c.tau;
+    c.norm_Q = h->norm_Q;
+    c.eps = INFINITY;
+    c.gamma_inner = p.gamma_inner;
+    c.eps_min = p.eps_min;
+    c.eps_fixed = p.eps_inner_fixed;
+    c.abar_scale = p.mprgp_abar_scale;
+    c.abar = p.mprgp_abar_scale / (c.norm_Q + c.inv_tau);
+    c.mprgp_gamma = p.mprgp_gamma;
+    c.max_inner = p.max_inner;
+    c.max_iter = p.max_iter;
+    c.theta = p.theta;
+    c.use_halpern = p.use_halpern;
+    c.has_unbounded_x = h->has_unbounded_x;
+    c.kp = p.kp; c.ki = p.ki; c.kd = p.kd;
+    c.rs_suff = p.restart_sufficient;
+    c.rs_nec = p.restart_necessary;
+    c.rs_art = p.restart_artificial;
+    c.tol = p.tol;
+    c.eps_inf = p.eps_inf;
+    c.c_max = h->c_max;
+    c.bscale_p = h->bscale_p;
+    c.gamma_q = h->gamma_q;
+}
+
+// Runs one inner solve (gradient at the warm start, then steps until the
+// device posts "done").  The host keeps `lag` steps queued beyond the last
+// status it has seen, so the GPU never waits for the host.
+int inner_solve(qp_handle* h, long long& gseq, int lag)
+{
+    DevState& S = h->S;
+    hipStream_t s = h->stream;
+    const long long base = gseq;
+    {
+        Timed t(h, QP_FAM_GINIT);
+        HIPCHK(launch_ginit(S, base, s));
+    }
+    volatile unsigned long long* word = h->hstat;
+    long long issued = 0;
+    for (;;) {
+        const long long target = issued - lag;
+        if (target >= 0) {
+            long long spins = 0;
+            for (;;) {
+                const unsigned long long w = *word;
+                const long long sq = (long long)(w >> 1);
+                if (sq >= base + target || (sq >= base && (w & 1ull))) break;
+                if ((++spins & 0x3ff) == 0) {
+                    const hipError_t q = hipStreamQuery(s);
+                    if (q == hipSuccess) {
+                        const unsigned long long w2 = *word;
+                        const long long s2 = (long long)(w2 >> 1);
+                        if (s2 >= base + target || (s2 >= base && (w2 & 1ull))) break;
+                        return fail(QP_ERR_DEVICE, "inner solver posted no status (internal error)");
+                    }
+                    if (q != hipErrorNotReady)
+                        return fail(QP_ERR_DEVICE, std::string("stream error: ") + hipGetErrorString(q));
+                }
+            }
+        }
+        const unsigned long long w = *word;
+        if ((long long)(w >> 1) >= base && (w & 1ull)) break;
+        ++issued;
+        {
+            Timed t(h, QP_FAM_DIR);
+            HIPCHK(launch_dir(S, s));
+        }
+        {
+            Timed t(h, QP_FAM_SPMV_HP);
+            HIPCHK(launch_hp(S, base + issued, s));
+        }
+        {
+            Timed t(h, QP_FAM_UPDATE);
+            HIPCHK(launch_update(S, base + issued, s));
+        }
+    }
+    gseq = base + issued + 1;
+    return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+qp_params qp_params_default(void)
+{
+    qp_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.tol = 1e-6;
+    p.max_iter = 100000;
+    p.check_every = 64;
+    p.max_inner = 500;
+    p.use_halpern = 1;
+    p.inner_lag = 2;
+    p.theta = 1.0;
+    p.kp = 0.99;
+    p.ki = 0.01;
+    p.kd = 0.0;
+    p.gamma_inner = 5e-4;
+    p.eps_min = 1e-9;
+    p.eps_inner_fixed = 0.0;
+    p.restart_sufficient = 0.2;
+    p.restart_necessary = 0.8;
+    p.restart_artificial = 0.36;
+    p.eps_inf = 1e-8;
+    p.eta_scale = 0.998;
+    p.norm_safety = 1.01;
+    p.power_tol = 1e-7;
+    p.power_max_iter = 1000;
+    p.mprgp_gamma = 1.0;
+    p.mprgp_abar_scale = 1.9;
+    p.timing = 0;
+    return p;
+}
+
+const char* qp_last_error(void) { return g_err.c_str(); }
+
+int qp_create(int64_t n, int64_t m, const int64_t* Q_rowptr, const int32_t* Q_col,
+              const double* Q_val, const int64_t* A_rowptr, const int32_t* A_col,
+              const double* A_val, const double* c, const double* b, const char* sense,
+              const double* lb, const double* ub, qp_handle** out)
+{
+    if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= INT32_MAX || m < 0 || m >= INT32_MAX)
+        return fail(QP_ERR_INVALID_ARG, "need 1 <= n < 2^31 and 0 <= m < 2^31");
+    if (m > 0 && (!b || !sense)) return fail(QP_ERR_INVALID_ARG, "b or sense is NULL");
+    int rc = check_vec("b", m, b, false);
+    if (m > 0 && rc) return rc;
+    std::vector<double> lc(m), uc(m);
+    for (int64_t i = 0; i < m; ++i) {
+        switch (sense[i]) {
+        case 'E': lc[i] = b[i]; uc[i] = b[i]; break;
+        case 'G': lc[i] = b[i]; uc[i] = INFINITY; break;
+        case 'L': lc[i] = -INFINITY; uc[i] = b[i]; break;
+        default: return fail(QP_ERR_INVALID_ARG, "sense: unknown character at row " + std::to_string(i));
+        }
+    }
+    return create_impl(n, m, Q_rowptr, Q_col, Q_val, A_rowptr, A_col, A_val, c, lc.data(),
+                       uc.data(), lb, ub, out);
+}
+
+int qp_create_ranged(int64_t n, int64_t m, const int64_t* Q_rowptr, const int32_t* Q_col,
+                     const double* Q_val, const int64_t* A_rowptr, const int32_t* A_col,
+                     const double* A_val, const double* c, const double* lc, const double* uc,
+                     const double* lb, const double* ub, qp_handle** out)
+{
+    if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= INT32_MAX || m < 0 || m >= INT32_MAX)
+        return fail(QP_ERR_INVALID_ARG, "need 1 <= n < 2^31 and 0 <= m < 2^31");
+    if (m > 0 && (!lc || !uc)) return fail(QP_ERR_INVALID_ARG, "lc or uc is NULL");
+    std::vector<double> l(m), u(m);
+    for (int64_t i = 0; i < m; ++i) { l[i] = lc[i]; u[i] = uc[i]; }
+    int rc = check_bounds("lc/uc", m, l.data(), u.data());
+    if (rc) return rc;
+    return create_impl(n, m, Q_rowptr, Q_col, Q_val, A_rowptr, A_col, A_val, c, l.data(),
+                       u.data(), lb, ub, out);
+}
+
+int qp_set_stream(qp_handle* h, void* stream)
+{
+    if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
+    h->stream = stream ? static_cast<hipStream_t>(stream) : h->own;
+    return 0;
+}
+
+void qp_destroy(qp_handle* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->dev_allocs) (void)hipFree(p);
+    for (EventPair& e : h->ev_pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (h->hstat) (void)hipHostFree(h->hstat);
+    if (h->own) (void)hipStreamDestroy(h->own);
+    delete h;
+}
+
+int qp_solve(qp_handle* h, double tol, int64_t max_iter)
+{
+    qp_params p = qp_params_default();
+    p.tol = tol;
+    p.max_iter = max_iter;
+    return qp_solve_ex(h, &p);
+}
+
+int qp_solve_ex(qp_handle* h, const qp_params* params)
+{
+    if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
+    const qp_params p = params ? *params : qp_params_default();
+    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 || p.max_inner < 0 || p.inner_lag < 0)
+        return fail(QP_ERR_INVALID_ARG, "invalid parameters");
+    DevState& S = h->S;
+    hipStream_t s = h->stream;
+    const double t0 = now_s();
+
+    h->timing = p.timing;
+    std::fill(h->fam_launches, h->fam_launches + QP_NFAM, 0);
+    h->ev_used = 0;
+    if (p.timing > 0 && h->ev_pool.empty()) {
+        h->ev_pool.resize(4096);
+        for (EventPair& e : h->ev_pool) {
+            HIPCHK(hipEventCreate(&e.a));
+            HIPCHK(hipEventCreate(&e.b));
+        }
+    }
+
+    Ctrl c;
+    setup_ctrl(h, p, c);
+    HIPCHK(hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_start(S, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->hstat[0] = 0;
+    h->hstat[1] = 0;
+
+    long long gseq = 1;
+    int64_t k = 0;
+    int status = QP_NOT_SOLVED;
+    for (;;) {
+        if (k > 0 || p.max_iter == 0) {
+            if (k % p.check_every == 0 || k >= p.max_iter) {
+                {
+                    Timed t(h, QP_FAM_CHECK);
+                    HIPCHK(launch_check(S, S.xt, S.yt, 1, h->has_unbounded_x, s));
+                    HIPCHK(launch_restart_copy(S, s));
+                }
+                HIPCHK(hipStreamSynchronize(s));
+                int st = 0;
+                HIPCHK(hipMemcpy(&st, &S.ctrl->status, sizeof(int), hipMemcpyDeviceToHost));
+                if (st != 0) {
+                    status = st;
+                    break;
+                }
+            }
+        }
+        if (k >= p.max_iter) {
+            status = QP_ITERATION_LIMIT;
+            break;
+        }
+        const int next_check = ((k + 1) % p.check_every == 0) || (k + 1 >= p.max_iter);
+        if (S.qdiag) {
+            Timed t(h, QP_FAM_RHS);
+            HIPCHK(launch_prox_diag(S, s));
+        } else {
+            {
+                Timed t(h, QP_FAM_RHS);
+                HIPCHK(launch_rhs(S, s));
+            }
+            int rc = inner_solve(h, gseq, p.inner_lag);
+            if (rc) return rc;
+        }
+        {
+            Timed t(h, QP_FAM_DUAL);
+            HIPCHK(launch_dual(S, next_check, s));
+        }
+        {
+            Timed t(h, QP_FAM_HALPX);
+            HIPCHK(launch_halpx(S, next_check, s));
+        }
+        ++k;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const double t1 = now_s();
+
+    Ctrl r;
+    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    qp_info& I = h->info;
+    std::memset(&I, 0, sizeof(I));
+    I.status = status;
+    I.iterations = r.k;
+    I.inner_iterations = r.inner_total;
+    I.restarts = r.restarts;
+    I.checks = r.checks;
+    I.r_primal = r.r_primal;
+    I.r_dual = r.r_dual;
+    I.r_gap = r.r_gap;
+    I.primal_obj = r.pobj;
+    I.dual_obj = r.dobj;
+    I.natural_residual = r.natural;
+    I.omega = r.omega;
+    I.eta = r.eta;
+    I.norm_A = h->norm_A;
+    I.norm_Q = h->norm_Q;
+    I.eps_inner = r.eps;
+    I.solve_seconds = t1 - t0;
+    I.setup_seconds = h->setup_seconds;
+    for (int f = 0; f < QP_NFAM; ++f) I.fam_launches[f] = h->fam_launches[f];
+    for (size_t i = 0; i < h->ev_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->ev_pool[i].a, h->ev_pool[i].b) == hipSuccess) {
+            I.fam_ms[h->ev_pool[i].fam] += ms;
+            I.fam_timed[h->ev_pool[i].fam] += 1;
+        }
+    }
+    h->status = status;
+    h->solved = 1;
+    g_err.clear();
+    return status;
+}
+
+int qp_result(const qp_handle* h, double* x, double* y, qp_info* info)
+{
+    if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->solved) return fail(QP_ERR_STATE, "no solve has run on this handle");
+    const DevState& S = h->S;
+    Ctrl r;
+    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (x) {
+        if (h->status == QP_DUAL_INFEASIBLE) {
+            HIPCHK(hipMemcpy(x, S.dx, sizeof(double) * h->n, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < h->n; ++i) x[i] /= r.d_max;
+        } else {
+            HIPCHK(hipMemcpy(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToHost));
+        }
+    }
+    if (y && h->m > 0) {
+        if (h->status == QP_PRIMAL_INFEASIBLE) {
+            HIPCHK(hipMemcpy(y, S.ytil, sizeof(double) * h->m, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < h->m; ++i) y[i] /= r.ytil_max;
+        } else {
+            HIPCHK(hipMemcpy(y, S.yt, sizeof(double) * h->m, hipMemcpyDeviceToHost));
+        }
+    }
+    if (info) *info = h->info;
+    return h->status;
+}
+
+int qp_apply(qp_handle* h, int op, const double* x, double* y)
+{
+    if (!h || !x || !y) return fail(QP_ERR_INVALID_ARG, "NULL argument");
+    const CsrDev* M = op == QP_OP_Q ? &h->S.Q : op == QP_OP_A ? &h->S.A : op == QP_OP_AT ? &h->S.AT : nullptr;
+    if (!M) return fail(QP_ERR_INVALID_ARG, "unknown operator");
+    HIPCHK(launch_spmv_plain(h->S, *M, x, y, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int qp_dot(qp_handle* h, int64_t len, const double* a, const double* b, double* out)
+{
+    if (!h || !out || len < 0 || len >= INT32_MAX || (len > 0 && (!a || !b)))
+        return fail(QP_ERR_INVALID_ARG, "bad argument");
+    HIPCHK(launch_dot(h->S, a, b, (int)len, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->hcheck[1], &h->S.ctrl->pw_norm, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::memcpy(out, &h->hcheck[1], sizeof(double));
+    return 0;
+}
+
+int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double eps,
+                  int64_t max_inner, int64_t* iters, double* res)
+{
+    if (!h || !rhs || !x || !(tau > 0.0) || max_inner < 0 || !(eps >= 0.0))
+        return fail(QP_ERR_INVALID_ARG, "bad argument");
+    DevState& S = h->S;
+    hipStream_t s = h->stream;
+    qp_params p = qp_params_default();
+    Ctrl c;
+    setup_ctrl(h, p, c);
+    c.tau = tau;
+    c.inv_tau = 1.0 / tau;
+    c.abar = p.mprgp_abar_scale / (c.norm_Q + c.inv_tau);
+    c.eps = eps;
+    c.eps_fixed = eps > 0.0 ? eps : 1e-300;
+    c.max_inner = max_inner;
+    HIPCHK(hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(S.rhs, rhs, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(S.xt, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->hstat[0] = 0;
+    long long gseq = 1;
+    int rc = inner_solve(h, gseq, 2);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Ctrl r;
+    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (iters) *iters = r.inner_it;
+    if (res) *res = r.res;
+    return 0;
+}
+
+int qp_kkt(qp_handle* h, const double* x, const double* y, double* out)
+{
+    if (!h || !x || (!y && h->m > 0) || !out) return fail(QP_ERR_INVALID_ARG, "NULL argument");
+    DevState& S = h->S;
+    hipStream_t s = h->stream;
+    Ctrl c;
+    setup_ctrl(h, qp_params_default(), c);
+    HIPCHK(hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_check(S, x, y ? y : S.y, 0, 0, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Ctrl r;
+    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    out[0] = r.r_primal; out[1] = r.r_dual; out[2] = r.r_gap;
+    out[3] = r.pobj; out[4] = r.dobj; out[5] = r.natural; out[6] = r.pviol;
+    return 0;
+}
+
+int64_t qp_spmv_schedule(int64_t rows, const int64_t* rowptr, int32_t* out, int64_t cap)
+{
+    if (rows < 0 || !rowptr) return fail(QP_ERR_INVALID_ARG, "bad argument");
+    std::vector<BlkDesc> blk;
+    int nlr = 0, nseg = 0;
+    build_plan(rows, rowptr, blk, nlr, nseg);
+    if (out)
+        for (int64_t i = 0; i < (int64_t)blk.size() && i < cap; ++i) {
+            const BlkDesc& b = blk[i];
+            const int32_t v[8] = {b.row0, b.nrows, b.k0, b.k1, b.lr, b.seg, b.nseg, b.seg_base};
+            std::memcpy(out + 8 * i, v, sizeof(v));
+        }
+    return (int64_t)blk.size();
+}
+
+int qp_norms(const qp_handle* h, double* norm_A, double* norm_Q)
+{
+    if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
+    if (norm_A) *norm_A = h->norm_A;
+    if (norm_Q) *norm_Q = h->norm_Q;
+    return 0;
+}
+
+}  // extern "C"

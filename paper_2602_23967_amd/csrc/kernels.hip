@@ -1,0 +1,1085 @@
+// kernels.hip -- gfx950 kernels of the PDHCG-II hot path.
+//
+// Every step of the method runs in one of two kernel shapes:
+//   k_spmv<E>  row-block CSR SpMV: a block stages up to NNZ_CAP products
+//              a_ij * x_j in LDS with coalesced loads of values and column
+//              indices, then sums each row with a lane group sized to the
+//              block's row count (1..64 lanes, wavefront shuffles), and hands
+//              the row sum to the fused epilogue E.  Rows longer than NNZ_CAP
+//              are split into segments whose partial sums are combined, in
+//              segment order, by the last segment block to arrive.
+//   k_vec<E>   grid-stride elementwise pass with epilogue E.
+// Both finish with a deterministic two-level reduction of up to 8 scalars
+// (wavefront xor-shuffle tree, then LDS across the block's 4 waves, then the
+// per-block partials summed in block order by the last block to arrive),
+// whose last block runs E::finalize: the scalar control logic of the method
+// (step lengths, inner-solver branch, tolerance, restart, PID, status).
+// No floating-point atomics are used, so every result is reproducible.
+#include <math.h>
+
+#include "pdhcg_internal.h"
+
+namespace pdhcg {
+
+enum { R_SUM = 0, R_MAX = 1, R_MIN = 2 };
+
+__device__ __forceinline__ double rcomb(int kind, double a, double b)
+{
+    if (kind == R_SUM) return a + b;
+    if (a != a) return a;
+    if (b != b) return b;
+    if (kind == R_MAX) return a > b ? a : b;
+    return a < b ? a : b;
+}
+
+// identities: every MAX slot reduces magnitudes, so 0 is its identity
+__device__ __forceinline__ double rid(int kind) { return kind == R_MIN ? INFINITY : 0.0; }
+
+__device__ __forceinline__ void st_agent(double* p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                       static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double ld_agent(const double* p)
+{
+    return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
+        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+
+__device__ __forceinline__ void post_status(unsigned long long* w, long long seq, int flag)
+{
+    __hip_atomic_store(w, (static_cast<unsigned long long>(seq) << 1) | (flag ? 1ull : 0ull),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __threadfence_system();
+}
+
+__device__ __forceinline__ double clampd(double v, double l, double u)
+{
+    return v < l ? l : (v > u ? u : v);
+}
+
+// sign set Y_i of a row (Section 2): {0} free, R+ upper only, R- lower only, R both
+__device__ __forceinline__ double projY(double v, double l, double u)
+{
+    const bool lf = isfinite(l), uf = isfinite(u);
+    if (lf && uf) return v;
+    if (uf) return v > 0.0 ? v : 0.0;
+    if (lf) return v < 0.0 ? v : 0.0;
+    return 0.0;
+}
+
+// sign set R_i of a variable (Section 2): {0} free, R- upper only, R+ lower only, R both
+__device__ __forceinline__ double projR(double v, double l, double u)
+{
+    const bool lf = isfinite(l), uf = isfinite(u);
+    if (lf && uf) return v;
+    if (uf) return v < 0.0 ? v : 0.0;
+    if (lf) return v > 0.0 ? v : 0.0;
+    return 0.0;
+}
+
+// recession cone of [l, u]: {0} bounded, R+ lower only, R- upper only, R free
+__device__ __forceinline__ double projRec(double v, double l, double u)
+{
+    const bool lf = isfinite(l), uf = isfinite(u);
+    if (lf && uf) return 0.0;
+    if (lf) return v > 0.0 ? v : 0.0;
+    if (uf) return v < 0.0 ? v : 0.0;
+    return v;
+}
+
+// terms of p(z; l, u) = u'z+ - l'z- (0 * inf = 0) and of its magnitude
+__device__ __forceinline__ double supp(double z, double l, double u)
+{
+    return z > 0.0 ? u * z : (z < 0.0 ? l * z : 0.0);
+}
+__device__ __forceinline__ double supp_abs(double z, double l, double u)
+{
+    return z > 0.0 ? fabs(u) * z : (z < 0.0 ? -fabs(l) * z : 0.0);
+}
+
+// Gradient split at a feasible x for the box QP (free gradient phi, chopped
+// gradient beta, reduced free gradient phit for step abar).
+struct Split {
+    double phi, beta, phit;
+};
+
+__device__ __forceinline__ Split split(double x, double g, double l, double u, double abar)
+{
+    Split s{0.0, 0.0, 0.0};
+    if (x > l && x < u) {
+        s.phi = g;
+        if (g > 0.0) s.phit = isfinite(l) ? fmin((x - l) / abar, g) : g;
+        else if (g < 0.0) s.phit = isfinite(u) ? fmax((x - u) / abar, g) : g;
+    } else if (l < u) {
+        if (x <= l) s.beta = g < 0.0 ? g : 0.0;
+        else s.beta = g > 0.0 ? g : 0.0;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+template <class E>
+__device__ __forceinline__ void block_reduce(double (&v)[E::NR > 0 ? E::NR : 1], double* lds)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] = rcomb(E::kind(j), v[j], __shfl_xor(v[j], off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) lds[wave * NR + j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            double r = lds[j];
+            for (int w = 1; w < TPB / 64; ++w) r = rcomb(E::kind(j), r, lds[w * NR + j]);
+            v[j] = r;
+        }
+    }
+    __syncthreads();
+}
+
+// Publishes the block's partials; returns true in the last block to arrive,
+// which then holds the grid totals in `tot`.
+template <class E>
+__device__ bool publish(double (&v)[E::NR > 0 ? E::NR : 1], double* partials, unsigned* counter,
+                        double* lds, double* tot)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ int s_last;
+    block_reduce<E>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) st_agent(&partials[(size_t)blockIdx.x * NR + j], v[j]);
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double r[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) r[j] = rid(E::kind(j));
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += TPB) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) r[j] = rcomb(E::kind(j), r[j], ld_agent(&partials[(size_t)b * NR + j]));
+    }
+    block_reduce<E>(r, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) tot[j] = r[j];
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    return true;
+}
+
+struct SumOne {
+    static constexpr int NR = 1;
+    __device__ static int kind(int) { return R_SUM; }
+};
+
+// ---------------------------------------------------------------------------
+// the two kernel shapes
+// ---------------------------------------------------------------------------
+
+template <class E>
+__global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials, unsigned* counter)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double prod[NNZ_CAP];
+    __shared__ double lds[NR * (TPB / 64)];
+    __shared__ double tot[NR];
+    __shared__ int s_seg_last;
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    const BlkDesc d = M.blk[blockIdx.x];
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+
+    const int cnt = d.k1 - d.k0;
+    {
+        int cj[NNZ_CAP / TPB];
+        double av[NNZ_CAP / TPB];
+#pragma unroll
+        for (int i = 0; i < NNZ_CAP / TPB; ++i) {
+            const int q = threadIdx.x + i * TPB;
+            cj[i] = q < cnt ? M.col[d.k0 + q] : -1;
+            av[i] = q < cnt ? M.val[d.k0 + q] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NNZ_CAP / TPB; ++i) {
+            const int q = threadIdx.x + i * TPB;
+            if (cj[i] >= 0) prod[q] = av[i] * e.xval(cj[i]);
+        }
+    }
+    __syncthreads();
+
+    if (d.nrows > 0) {
+        int G = 64;
+        while (G > 1 && G * d.nrows > TPB) G >>= 1;
+        const int grp = threadIdx.x / G, lane = threadIdx.x - grp * G;
+        if (grp < d.nrows) {
+            const int row = d.row0 + grp;
+            const int a = M.rowptr[row] - d.k0, b = M.rowptr[row + 1] - d.k0;
+            double s = 0.0;
+            for (int i = a + lane; i < b; i += G) s += prod[i];
+            for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+            if (lane == 0) e.row(row, s, acc);
+        }
+    } else if (d.nseg > 0) {
+        double s[1] = {0.0};
+        for (int q = threadIdx.x; q < cnt; q += TPB) s[0] += prod[q];
+        block_reduce<SumOne>(s, lds);
+        if (threadIdx.x == 0) {
+            st_agent(&M.seg_part[d.seg_base + d.seg], s[0]);
+            __threadfence();
+            const unsigned prev = atomicAdd(&M.lr_count[d.lr], 1u);
+            s_seg_last = prev == (unsigned)(d.nseg - 1);
+        }
+        __syncthreads();
+        if (s_seg_last && threadIdx.x == 0) {
+            __threadfence();
+            double total = 0.0;
+            for (int i = 0; i < d.nseg; ++i) total += ld_agent(&M.seg_part[d.seg_base + i]);
+            __hip_atomic_store(&M.lr_count[d.lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            e.row(d.row0, total, acc);
+        }
+    }
+    if constexpr (E::NR > 0) {
+        if (publish<E>(acc, partials, counter, lds, tot) && threadIdx.x == 0) e.finalize(tot);
+    }
+}
+
+template <class E>
+__global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* partials, unsigned* counter)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double lds[NR * (TPB / 64)];
+    __shared__ double tot[NR];
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+    const long long stride = (long long)gridDim.x * TPB;
+    for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < len; i += stride) e.elem(i, acc);
+    if constexpr (E::NR > 0) {
+        if (publish<E>(acc, partials, counter, lds, tot) && threadIdx.x == 0) e.finalize(tot);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// epilogues
+// ---------------------------------------------------------------------------
+
+struct EpiBase {
+    Ctrl* ctrl;
+    __device__ bool skip() const { return false; }
+    __device__ void init() {}
+    __device__ static int kind(int) { return R_SUM; }
+    __device__ void finalize(const double*) const {}
+};
+
+template <int N>
+using Acc = double (&)[N > 0 ? N : 1];
+
+// decision shared by every point where the inner solver has fresh split
+// statistics: stop test (Section 3.3 tolerance), proportioning test, and the
+// kind of the next direction
+__device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long long seq,
+                             unsigned long long* dstat)
+{
+    c->gp2 = gp2; c->b2 = b2; c->ptp = ptp;
+    c->res = sqrt(gp2);
+    const double eps = c->eps_fixed > 0.0 ? c->eps_fixed : c->eps;
+    c->done = (c->res <= eps || c->inner_it >= c->max_inner) ? 1 : 0;
+    const int prop = b2 <= c->mprgp_gamma * c->mprgp_gamma * ptp;
+    c->proportional = prop;
+    c->dir_mode = !prop ? DIR_BETA : (c->last_step == STEP_CG ? DIR_CONJ : DIR_PHI);
+    post_status(dstat, seq, c->done);
+}
+
+// primal step, diagonal Q (Section 2.2 closed form), fused into A'y:
+//   x_T = clip((x/tau - c - A'y) / (q + 1/tau), l_v, u_v)
+struct EpiProx : EpiBase {
+    static constexpr int NR = 0;
+    const double *y, *x, *c, *qd, *lv, *uv;
+    double* xt;
+    double it;
+    __device__ void init() { it = ctrl->inv_tau; }
+    __device__ double xval(int j) const { return y[j]; }
+    __device__ void row(int i, double s, Acc<NR>) const
+    {
+        xt[i] = clampd((x[i] * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
+    }
+};
+
+// rhs of the primal subproblem (eq. primal_update): rhs = x/tau - c - A'y
+struct EpiRhs : EpiBase {
+    static constexpr int NR = 0;
+    const double *y, *x, *c;
+    double* rhs;
+    double it;
+    __device__ void init() { it = ctrl->inv_tau; }
+    __device__ double xval(int j) const { return y[j]; }
+    __device__ void row(int i, double s, Acc<NR>) const { rhs[i] = x[i] * it - c[i] - s; }
+};
+
+// gradient of the subproblem at the (clipped) warm start: g = Q x + x/tau - rhs,
+// with split statistics; finalize starts the inner solve
+struct EpiGinit : EpiBase {
+    static constexpr int NR = 3;
+    double* xt;
+    const double *rhs, *lv, *uv;
+    double* g;
+    unsigned long long* dstat;
+    long long seq;
+    double it, abar;
+    __device__ void init() { it = ctrl->inv_tau; abar = ctrl->abar; }
+    __device__ double xval(int j) const { return clampd(xt[j], lv[j], uv[j]); }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double xi = clampd(xt[i], lv[i], uv[i]);
+        xt[i] = xi;
+        const double gi = s + it * xi - rhs[i];
+        g[i] = gi;
+        const Split sp = split(xi, gi, lv[i], uv[i], abar);
+        a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+        a[1] += sp.beta * sp.beta;
+        a[2] += sp.phit * sp.phi;
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* c = ctrl;
+        c->inner_it = 0;
+        c->last_step = STEP_NONE;
+        c->need_g = 0;
+        c->skip_update = 0;
+        if (isinf(c->eps) && c->eps_fixed <= 0.0) c->eps = fmax(c->gamma_inner * sqrt(t[0]), c->eps_min);
+        inner_decide(c, t[0], t[1], t[2], seq, dstat);
+    }
+};
+
+// inner step, part A: H p = Q p + p/tau with p'Hp, g'p and the feasible
+// step; or, right after an expansion step, the fresh gradient g = H x - rhs
+struct EpiStepA : EpiBase {
+    static constexpr int NR = 4;
+    const double *p, *lv, *uv, *rhs;
+    double *xt, *g, *hp;
+    unsigned long long* dstat;
+    long long seq;
+    double it, abar;
+    int ng;
+    __device__ static int kind(int j) { return j == 3 ? R_MIN : R_SUM; }
+    __device__ bool skip() const { return ctrl->done != 0; }
+    __device__ void init() { it = ctrl->inv_tau; abar = ctrl->abar; ng = ctrl->need_g; }
+    __device__ double xval(int j) const { return ng ? xt[j] : p[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        if (ng) {
+            const double xi = xt[i];
+            const double gi = s + it * xi - rhs[i];
+            g[i] = gi;
+            const Split sp = split(xi, gi, lv[i], uv[i], abar);
+            a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+            a[1] += sp.beta * sp.beta;
+            a[2] += sp.phit * sp.phi;
+        } else {
+            const double pi = p[i], xi = xt[i];
+            const double h = s + it * pi;
+            hp[i] = h;
+            a[0] += pi * h;
+            a[1] += g[i] * pi;
+            double st = INFINITY;
+            if (pi > 0.0 && isfinite(lv[i])) st = (xi - lv[i]) / pi;
+            else if (pi < 0.0 && isfinite(uv[i])) st = (xi - uv[i]) / pi;
+            a[3] = fmin(a[3], st);
+        }
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* c = ctrl;
+        if (ng) {
+            c->need_g = 0;
+            c->skip_update = 1;
+            inner_decide(c, t[0], t[1], t[2], seq, dstat);
+            return;
+        }
+        c->skip_update = 0;
+        const double pHp = t[0], gp = t[1];
+        double af = t[3] < 0.0 ? 0.0 : t[3];
+        if (!(pHp > 0.0)) {   // no descent direction left: stop
+            c->done = 1;
+            c->skip_update = 1;
+            post_status(dstat, seq, 1);
+            return;
+        }
+        c->pHp = pHp;
+        const double acg = gp / pHp;
+        if (c->dir_mode == DIR_BETA) {
+            c->step_kind = STEP_PROP;
+            c->alpha = acg < af ? acg : af;
+        } else if (acg <= af) {
+            c->step_kind = STEP_CG;
+            c->alpha = acg;
+        } else {
+            c->step_kind = STEP_EXPAND;
+            c->alpha = af;
+        }
+    }
+};
+
+// inner step, part B: x <- clip(x - alpha p), g <- g - alpha Hp; expansion
+// adds the projected step x <- clip(x - abar phi(x)) and asks for a fresh g
+struct EpiStepB : EpiBase {
+    static constexpr int NR = 4;
+    const double *p, *hp, *lv, *uv;
+    double *xt, *g;
+    unsigned long long* dstat;
+    long long seq;
+    double alpha, abar;
+    int kindstep;
+    __device__ bool skip() const { return ctrl->done != 0 || ctrl->skip_update != 0; }
+    __device__ void init() { alpha = ctrl->alpha; abar = ctrl->abar; kindstep = ctrl->step_kind; }
+    __device__ void elem(long long i, Acc<NR> a) const
+    {
+        const double l = lv[i], u = uv[i];
+        double xi = clampd(xt[i] - alpha * p[i], l, u);
+        const double gi = g[i] - alpha * hp[i];
+        g[i] = gi;
+        const Split sp = split(xi, gi, l, u, abar);
+        if (kindstep == STEP_EXPAND) {
+            xi = clampd(xi - abar * sp.phi, l, u);
+        } else {
+            a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+            a[1] += sp.beta * sp.beta;
+            a[2] += sp.phit * sp.phi;
+            a[3] += sp.phi * hp[i];
+        }
+        xt[i] = xi;
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* c = ctrl;
+        c->inner_it += 1;
+        c->inner_total += 1;
+        if (kindstep == STEP_EXPAND) {
+            c->last_step = STEP_EXPAND;
+            c->need_g = 1;
+            post_status(dstat, seq, 0);
+            return;
+        }
+        if (kindstep == STEP_CG) c->gam = t[3] / c->pHp;
+        c->last_step = kindstep;
+        inner_decide(c, t[0], t[1], t[2], seq, dstat);
+    }
+};
+
+// next direction: beta (proportioning), phi, or phi - gam p (conjugate)
+struct EpiDir : EpiBase {
+    static constexpr int NR = 0;
+    const double *xt, *g, *lv, *uv;
+    double* p;
+    double gam, abar;
+    int mode;
+    __device__ bool skip() const { return ctrl->done != 0 || ctrl->need_g != 0; }
+    __device__ void init() { gam = ctrl->gam; abar = ctrl->abar; mode = ctrl->dir_mode; }
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        const Split sp = split(xt[i], g[i], lv[i], uv[i], abar);
+        p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
+    }
+};
+
+// dual step (eqs. extrapolation, dual_update) with x_bar = 2 x_T - x formed
+// on the fly, then the reflected Halpern average of y (Section 3.1)
+struct EpiDual : EpiBase {
+    static constexpr int NR = 4;
+    const double *xt, *x, *ya, *lc, *uc;
+    double *y, *yt, *ytil;
+    int store;
+    double sigma, w, wa, th;
+    int halpern;
+    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
+    __device__ void init()
+    {
+        sigma = ctrl->sigma;
+        const double t = (double)ctrl->t;
+        w = (t + 1.0) / (t + 2.0);
+        wa = 1.0 / (t + 2.0);
+        th = ctrl->theta;
+        halpern = ctrl->use_halpern;
+    }
+    __device__ double xval(int j) const { return 2.0 * xt[j] - x[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double yi = y[i], l = lc[i], u = uc[i];
+        const double v = yi / sigma + s;
+        const double yti = sigma * (v - clampd(v, l, u));
+        const double dy = yti - yi;
+        a[0] += dy * dy;
+        yt[i] = yti;
+        y[i] = halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
+        if (store) {
+            const double yy = projY(dy, l, u);
+            ytil[i] = yy;
+            a[1] = rcomb(R_MAX, a[1], fabs(yy));
+            a[2] += supp(yy, l, u);
+            a[3] += supp_abs(yy, l, u);
+        }
+    }
+    __device__ void finalize(const double* t) const
+    {
+        ctrl->ndy2 = t[0];
+        if (store) {
+            ctrl->ytil_max = t[1];
+            ctrl->ptil_sum = t[2];
+            ctrl->ptil_abs = t[3];
+        }
+    }
+};
+
+// Halpern average of x, movement norm, inner-tolerance update (Section 3.3)
+// and the iteration counters
+struct EpiHalpX : EpiBase {
+    static constexpr int NR = 3;
+    const double *xt, *xa, *c, *lv, *uv;
+    double *x, *d;
+    int store;
+    double w, wa, th;
+    int halpern, unb;
+    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
+    __device__ void init()
+    {
+        const double t = (double)ctrl->t;
+        w = (t + 1.0) / (t + 2.0);
+        wa = 1.0 / (t + 2.0);
+        th = ctrl->theta;
+        halpern = ctrl->use_halpern;
+        unb = ctrl->has_unbounded_x;
+    }
+    __device__ void elem(long long i, Acc<NR> a) const
+    {
+        const double xti = xt[i], xi = x[i];
+        const double dxi = xti - xi;
+        a[0] += dxi * dxi;
+        x[i] = halpern ? w * ((1.0 + th) * xti - th * xi) + wa * xa[i] : xti;
+        if (store && unb) {
+            const double di = projRec(dxi, lv[i], uv[i]);
+            d[i] = di;
+            a[1] = rcomb(R_MAX, a[1], fabs(di));
+            a[2] += c[i] * di;
+        }
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* C = ctrl;
+        C->ndx2 = t[0];
+        if (store) {
+            C->d_max = unb ? t[1] : 0.0;
+            C->cd = unb ? t[2] : 0.0;
+        }
+        if (C->eps_fixed <= 0.0)
+            C->eps = fmin(C->eps, fmax(C->gamma_inner * C->omega * sqrt(t[0]) / C->tau, C->eps_min));
+        C->k += 1;
+        C->t += 1;
+        if (C->t == 1) C->R_start = sqrt(C->omega * t[0] + C->ndy2 / C->omega);
+    }
+};
+
+// ---- check kernels (Sections 4 and 5) -------------------------------------
+
+// w = A' ytil: violation of A'ytil in R and p(-proj_R(A'ytil); l_v, u_v)
+struct EpiPinf : EpiBase {
+    static constexpr int NR = 3;
+    const double *ytil, *lv, *uv;
+    __device__ static int kind(int j) { return j == 0 ? R_MAX : R_SUM; }
+    __device__ double xval(int j) const { return ytil[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double wh = projR(s, lv[i], uv[i]);
+        a[0] = rcomb(R_MAX, a[0], fabs(s - wh));
+        a[1] += supp(-wh, lv[i], uv[i]);
+        a[2] += supp_abs(-wh, lv[i], uv[i]);
+    }
+    __device__ void finalize(const double* t) const
+    {
+        ctrl->w_viol = t[0];
+        ctrl->pw_sum = t[1];
+        ctrl->pw_abs = t[2];
+    }
+};
+
+// A d: violation of A d in Recc(S)
+struct EpiAd : EpiBase {
+    static constexpr int NR = 1;
+    const double *d, *lc, *uc;
+    __device__ static int kind(int) { return R_MAX; }
+    __device__ double xval(int j) const { return d[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        a[0] = rcomb(R_MAX, a[0], fabs(s - projRec(s, lc[i], uc[i])));
+    }
+    __device__ void finalize(const double* t) const { ctrl->ad_viol = t[0]; }
+};
+
+// Q d: its largest magnitude
+struct EpiQd : EpiBase {
+    static constexpr int NR = 1;
+    const double* d;
+    __device__ static int kind(int) { return R_MAX; }
+    __device__ double xval(int j) const { return d[j]; }
+    __device__ void row(int, double s, Acc<NR> a) const { a[0] = rcomb(R_MAX, a[0], fabs(s)); }
+    __device__ void finalize(const double* t) const { ctrl->qd_max = t[0]; }
+};
+
+// A' y written out, with ||A'y||_inf
+struct EpiAty : EpiBase {
+    static constexpr int NR = 1;
+    const double* y;
+    double* aty;
+    __device__ static int kind(int) { return R_MAX; }
+    __device__ double xval(int j) const { return y[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        aty[i] = s;
+        a[0] = rcomb(R_MAX, a[0], fabs(s));
+    }
+    __device__ void finalize(const double* t) const { ctrl->aty_max = t[0]; }
+};
+
+// A x: primal violation, p(y; l_c, u_c), and the dual movement of the round
+struct EpiAx : EpiBase {
+    static constexpr int NR = 3;
+    const double *x, *y, *ya, *lc, *uc;
+    __device__ static int kind(int j) { return j == 0 ? R_MAX : R_SUM; }
+    __device__ double xval(int j) const { return x[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double l = lc[i], u = uc[i], yi = y[i];
+        a[0] = rcomb(R_MAX, a[0], fabs(s - clampd(s, l, u)));
+        a[1] += supp(yi, l, u);
+        if (ya) {
+            const double dv = yi - ya[i];
+            a[2] += dv * dv;
+        }
+    }
+    __device__ void finalize(const double* t) const
+    {
+        ctrl->pviol = t[0];
+        ctrl->py_sum = t[1];
+        ctrl->mvy2 = t[2];
+    }
+};
+
+__device__ bool primal_infeasible(const Ctrl* c)
+{
+    if (!(c->ytil_max > 0.0) || !isfinite(c->ytil_max)) return false;
+    const double val = c->pw_sum + c->ptil_sum;
+    const double imp = val < 0.0 ? -val : 0.0;
+    const double mag = c->pw_abs + c->ptil_abs;
+    return imp > 1e-9 * mag && c->w_viol <= c->eps_inf * imp;
+}
+
+__device__ bool dual_infeasible(const Ctrl* c)
+{
+    if (!c->has_unbounded_x || !(c->d_max > 0.0) || !isfinite(c->d_max)) return false;
+    if (!(c->cd / c->d_max < -c->tol)) return false;
+    const double v1 = c->ad_viol / c->d_max;
+    const double v2 = c->qd_max / c->d_max / c->gamma_q;
+    return (v1 > v2 ? v1 : v2) <= c->eps_inf;
+}
+
+// Q x with r = Qx + c + A'y: dual violation, norms, objective pieces, gap
+// terms, natural residual and the primal movement of the round; when `full`,
+// finalize makes the termination / infeasibility / restart decision
+struct EpiQx : EpiBase {
+    static constexpr int NR = 7;
+    const double *x, *xa, *c, *aty, *lv, *uv;
+    unsigned long long* dcheck;
+    int full;
+    __device__ static int kind(int j) { return (j == 0 || j == 1 || j == 5) ? R_MAX : R_SUM; }
+    __device__ double xval(int j) const { return x[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double xi = x[i], l = lv[i], u = uv[i];
+        const double r = s + c[i] + aty[i];
+        const double rh = projR(r, l, u);
+        a[0] = rcomb(R_MAX, a[0], fabs(r - rh));
+        a[1] = rcomb(R_MAX, a[1], fabs(s));
+        a[2] += xi * s;
+        a[3] += c[i] * xi;
+        a[4] += supp(-rh, l, u);
+        a[5] = rcomb(R_MAX, a[5], fabs(xi - clampd(xi - r, l, u)));
+        if (xa) {
+            const double dv = xi - xa[i];
+            a[6] += dv * dv;
+        }
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* C = ctrl;
+        C->dviol = t[0]; C->qx_max = t[1]; C->xqx = t[2]; C->cx = t[3];
+        C->pr_sum = t[4]; C->natural = t[5]; C->mvx2 = t[6];
+        C->r_primal = C->pviol / C->bscale_p;
+        double sd = C->qx_max > C->aty_max ? C->qx_max : C->aty_max;
+        sd = sd > C->c_max ? sd : C->c_max;
+        C->r_dual = C->dviol / (1.0 + sd);
+        C->pobj = 0.5 * C->xqx + C->cx;
+        const double dneg = 0.5 * C->xqx + C->pr_sum + C->py_sum;
+        C->dobj = -dneg;
+        const double gap = fabs(C->xqx + C->cx + C->pr_sum + C->py_sum);
+        const double den = fabs(C->pobj) > fabs(dneg) ? fabs(C->pobj) : fabs(dneg);
+        C->r_gap = gap / (1.0 + den);
+        if (!full) return;
+
+        C->checks += 1;
+        double worst = C->r_primal > C->r_dual ? C->r_primal : C->r_dual;
+        worst = worst > C->r_gap ? worst : C->r_gap;
+        int st = 0, restart = 0;
+        if (!isfinite(worst) || worst != worst) st = 5;
+        else if (worst <= C->tol) st = 1;
+        else if (C->k > 0 && primal_infeasible(C)) st = 2;
+        else if (C->k > 0 && dual_infeasible(C)) st = 3;
+        else if (C->k >= C->max_iter) st = 4;
+        else {
+            // restart rule on the weighted fixed-point residual of the last step
+            const double R = sqrt(C->omega * C->ndx2 + C->ndy2 / C->omega);
+            restart = R <= C->rs_suff * C->R_start ||
+                      (C->R_prev_valid && R <= C->rs_nec * C->R_start && R > C->R_prev) ||
+                      (double)C->t >= C->rs_art * (double)C->k;
+            C->R_prev = R;
+            C->R_prev_valid = 1;
+            if (restart) {
+                // PID on log(omega) over the round (Section 3.2, eq. pid)
+                const double mx = sqrt(C->mvx2), my = sqrt(C->mvy2);
+                if (mx > 1e-10 && my > 1e-10 && isfinite(mx) && isfinite(my)) {
+                    const double so = sqrt(C->omega);
+                    const double e = log(so * mx / (my / so));
+                    C->pid_int += e;
+                    double lw = log(C->omega) - (C->kp * e + C->ki * C->pid_int + C->kd * (e - C->pid_prev));
+                    const double lo = log(C->omega0) - 10.0, hi = log(C->omega0) + 10.0;
+                    lw = lw < lo ? lo : (lw > hi ? hi : lw);
+                    C->omega = exp(lw);
+                    C->pid_prev = e;
+                }
+                C->tau = C->eta / C->omega;
+                C->sigma = C->eta * C->omega;
+                C->inv_tau = 1.0 / C->tau;
+                C->abar = C->abar_scale / (C->norm_Q + C->inv_tau);
+                C->t = 0;
+                C->R_prev_valid = 0;
+                C->restarts += 1;
+            }
+        }
+        C->status = st;
+        C->restart_pending = restart;
+        C->pinf = st == 2;
+        C->dinf = st == 3;
+        post_status(dcheck, C->checks, st != 0);
+    }
+};
+
+// restart: x, anchor <- x_T; y, anchor <- y_T
+struct EpiRestart : EpiBase {
+    static constexpr int NR = 0;
+    const double *xt, *yt;
+    double *x, *xa, *y, *ya;
+    int n;
+    __device__ bool skip() const { return ctrl->restart_pending == 0; }
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        if (i < n) {
+            x[i] = xt[i];
+            xa[i] = xt[i];
+        } else {
+            const long long j = i - n;
+            y[j] = yt[j];
+            ya[j] = yt[j];
+        }
+    }
+};
+
+// start point x0 = proj_X(0), y0 = 0, anchors and T(z) set to the start
+struct EpiStart : EpiBase {
+    static constexpr int NR = 0;
+    const double *lv, *uv;
+    double *x, *xa, *xt, *y, *ya, *yt;
+    int n;
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        if (i < n) {
+            const double v = clampd(0.0, lv[i], uv[i]);
+            x[i] = v; xa[i] = v; xt[i] = v;
+        } else {
+            const long long j = i - n;
+            y[j] = 0.0; ya[j] = 0.0; yt[j] = 0.0;
+        }
+    }
+};
+
+// SplitMix64 output for counter i with seed 0 (Steele, Lea and Flood 2014),
+// mapped to [-1, 1): the power-iteration start vector, with its squared norm
+struct EpiPowerStart : EpiBase {
+    static constexpr int NR = 1;
+    double* v;
+    __device__ void elem(long long i, Acc<NR> a) const
+    {
+        unsigned long long z = (static_cast<unsigned long long>(i) + 1ull) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+        const double val = 2.0 * u - 1.0;
+        v[i] = val;
+        a[0] += val * val;
+    }
+    __device__ void finalize(const double* t) const { ctrl->pw_norm = sqrt(t[0]); }
+};
+
+// y = M x with ||y||_2 left in ctrl->pw_norm
+struct EpiNorm : EpiBase {
+    static constexpr int NR = 1;
+    const double* x;
+    double* y;
+    __device__ double xval(int j) const { return x[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        y[i] = s;
+        a[0] += s * s;
+    }
+    __device__ void finalize(const double* t) const { ctrl->pw_norm = sqrt(t[0]); }
+};
+
+// v <- v / ctrl->pw_norm
+struct EpiScale : EpiBase {
+    static constexpr int NR = 0;
+    double* v;
+    double inv;
+    __device__ void init() { inv = 1.0 / ctrl->pw_norm; }
+    __device__ void elem(long long i, Acc<NR>) const { v[i] *= inv; }
+};
+
+struct EpiPlain : EpiBase {
+    static constexpr int NR = 0;
+    const double* x;
+    double* y;
+    __device__ double xval(int j) const { return x[j]; }
+    __device__ void row(int i, double s, Acc<NR>) const { y[i] = s; }
+};
+
+struct EpiDot : EpiBase {
+    static constexpr int NR = 1;
+    const double *a, *b;
+    __device__ void elem(long long i, Acc<NR> acc) const { acc[0] += a[i] * b[i]; }
+    __device__ void finalize(const double* t) const { ctrl->pw_norm = t[0]; }
+};
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+int vec_grid(long long len)
+{
+    long long g = (len + TPB - 1) / TPB;
+    if (g < 1) g = 1;
+    if (g > VEC_GRID_MAX) g = VEC_GRID_MAX;
+    return (int)g;
+}
+
+template <class E>
+static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s)
+{
+    k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials, S.counter);
+    return hipGetLastError();
+}
+
+template <class E>
+static hipError_t run_vec(const DevState& S, long long len, const E& e, hipStream_t s)
+{
+    k_vec<E><<<vec_grid(len), TPB, 0, s>>>(len, e, S.partials, S.counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_start(const DevState& S, hipStream_t s)
+{
+    EpiStart e{};
+    e.ctrl = S.ctrl;
+    e.lv = S.lv; e.uv = S.uv;
+    e.x = S.x; e.xa = S.xa; e.xt = S.xt; e.y = S.y; e.ya = S.ya; e.yt = S.yt;
+    e.n = S.n;
+    return run_vec(S, (long long)S.n + S.m, e, s);
+}
+
+hipError_t launch_prox_diag(const DevState& S, hipStream_t s)
+{
+    EpiProx e{};
+    e.ctrl = S.ctrl;
+    e.y = S.y; e.x = S.x; e.c = S.c; e.qd = S.qd; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt;
+    return run_spmv(S, S.AT, e, s);
+}
+
+hipError_t launch_rhs(const DevState& S, hipStream_t s)
+{
+    EpiRhs e{};
+    e.ctrl = S.ctrl;
+    e.y = S.y; e.x = S.x; e.c = S.c; e.rhs = S.rhs;
+    return run_spmv(S, S.AT, e, s);
+}
+
+hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s)
+{
+    EpiGinit e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.rhs = S.rhs; e.lv = S.lv; e.uv = S.uv; e.g = S.g;
+    e.dstat = S.dstat; e.seq = seq;
+    return run_spmv(S, S.Q, e, s);
+}
+
+hipError_t launch_dir(const DevState& S, hipStream_t s)
+{
+    EpiDir e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.g = S.g; e.lv = S.lv; e.uv = S.uv; e.p = S.p;
+    return run_vec(S, S.n, e, s);
+}
+
+hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s)
+{
+    EpiStepA e{};
+    e.ctrl = S.ctrl;
+    e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
+    e.dstat = S.dstat; e.seq = seq;
+    return run_spmv(S, S.Q, e, s);
+}
+
+hipError_t launch_update(const DevState& S, long long seq, hipStream_t s)
+{
+    EpiStepB e{};
+    e.ctrl = S.ctrl;
+    e.p = S.p; e.hp = S.hp; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt; e.g = S.g;
+    e.dstat = S.dstat; e.seq = seq;
+    return run_vec(S, S.n, e, s);
+}
+
+hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s)
+{
+    EpiDual e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.x = S.x; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
+    e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
+    return run_spmv(S, S.A, e, s);
+}
+
+hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s)
+{
+    EpiHalpX e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.xa = S.xa; e.c = S.c; e.lv = S.lv; e.uv = S.uv; e.x = S.x; e.d = S.dx;
+    e.store = store_delta;
+    return run_vec(S, S.n, e, s);
+}
+
+hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
+                        hipStream_t s)
+{
+    hipError_t err;
+    if (full) {
+        // certificate pieces first: the decision is taken in the last kernel
+        EpiPinf ep{};
+        ep.ctrl = S.ctrl;
+        ep.ytil = S.ytil; ep.lv = S.lv; ep.uv = S.uv;
+        if ((err = run_spmv(S, S.AT, ep, s)) != hipSuccess) return err;
+        if (dinf) {
+            EpiAd ea{};
+            ea.ctrl = S.ctrl;
+            ea.d = S.dx; ea.lc = S.lc; ea.uc = S.uc;
+            if ((err = run_spmv(S, S.A, ea, s)) != hipSuccess) return err;
+            EpiQd eqd{};
+            eqd.ctrl = S.ctrl;
+            eqd.d = S.dx;
+            if ((err = run_spmv(S, S.Q, eqd, s)) != hipSuccess) return err;
+        }
+    }
+    EpiAty et{};
+    et.ctrl = S.ctrl;
+    et.y = y; et.aty = S.aty;
+    if ((err = run_spmv(S, S.AT, et, s)) != hipSuccess) return err;
+    EpiAx ex{};
+    ex.ctrl = S.ctrl;
+    ex.x = x; ex.y = y; ex.ya = full ? S.ya : nullptr; ex.lc = S.lc; ex.uc = S.uc;
+    if ((err = run_spmv(S, S.A, ex, s)) != hipSuccess) return err;
+    EpiQx eq{};
+    eq.ctrl = S.ctrl;
+    eq.x = x; eq.xa = full ? S.xa : nullptr; eq.c = S.c; eq.aty = S.aty; eq.lv = S.lv; eq.uv = S.uv;
+    eq.dcheck = S.dcheck; eq.full = full;
+    return run_spmv(S, S.Q, eq, s);
+}
+
+hipError_t launch_restart_copy(const DevState& S, hipStream_t s)
+{
+    EpiRestart e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.yt = S.yt; e.x = S.x; e.xa = S.xa; e.y = S.y; e.ya = S.ya; e.n = S.n;
+    return run_vec(S, (long long)S.n + S.m, e, s);
+}
+
+hipError_t launch_power_start(const DevState& S, double* v, int len, hipStream_t s)
+{
+    EpiPowerStart e{};
+    e.ctrl = S.ctrl;
+    e.v = v;
+    return run_vec(S, len, e, s);
+}
+
+hipError_t launch_spmv_norm(const DevState& S, const CsrDev& M, const double* x, double* y,
+                            hipStream_t s)
+{
+    EpiNorm e{};
+    e.ctrl = S.ctrl;
+    e.x = x; e.y = y;
+    return run_spmv(S, M, e, s);
+}
+
+hipError_t launch_scale(const DevState& S, double* v, int len, hipStream_t s)
+{
+    EpiScale e{};
+    e.ctrl = S.ctrl;
+    e.v = v;
+    return run_vec(S, len, e, s);
+}
+
+hipError_t launch_spmv_plain(const DevState& S, const CsrDev& M, const double* x, double* y,
+                             hipStream_t s)
+{
+    EpiPlain e{};
+    e.ctrl = S.ctrl;
+    e.x = x; e.y = y;
+    return run_spmv(S, M, e, s);
+}
+
+hipError_t launch_dot(const DevState& S, const double* a, const double* b, int len, hipStream_t s)
+{
+    EpiDot e{};
+    e.ctrl = S.ctrl;
+    e.a = a; e.b = b;
+    return run_vec(S, len, e, s);
+}
+
+}  // namespace pdhcg

@@ -1,0 +1,129 @@
+// pdhcg_internal.h -- device-side data layout shared by the host driver
+// (host.cpp) and the gfx950 kernels (kernels.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdhcg {
+
+constexpr int TPB = 256;        // threads per block for every kernel
+constexpr int NNZ_CAP = 2048;   // nonzeros staged in LDS per row block
+constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at most)
+constexpr int VEC_GRID_MAX = 2048;
+
+// One work item of the row-block SpMV schedule.
+//   nrows > 0            rows [row0, row0+nrows), nonzeros [k0, k1)
+//   nrows == 0, nseg > 0 segment `seg` of long row row0 (nonzeros [k0, k1));
+//                        partial sums land in seg_part[seg_base + seg] and the
+//                        last segment to arrive (counter lr) finishes the row
+//   nrows == 0, nseg == 0 empty item (keeps a grid of >= 1 block)
+struct BlkDesc {
+    int row0, nrows, k0, k1;
+    int lr, seg, nseg, seg_base;
+};
+
+struct CsrDev {
+    int rows = 0, cols = 0;
+    long long nnz = 0;
+    int* rowptr = nullptr;     // rows + 1
+    int* col = nullptr;
+    double* val = nullptr;
+    BlkDesc* blk = nullptr;
+    int nblk = 0;
+    double* seg_part = nullptr;
+    unsigned* lr_count = nullptr;
+};
+
+// inner-solver direction kinds
+enum { DIR_PHI = 0, DIR_CONJ = 1, DIR_BETA = 2 };
+// last inner step kinds
+enum { STEP_NONE = 0, STEP_CG = 1, STEP_EXPAND = 2, STEP_PROP = 3 };
+
+// Device control block: every scalar of the method lives here, so the
+// whole iteration runs without host round trips.
+struct Ctrl {
+    // step sizes (Section 3.2)
+    double omega, omega0, eta, tau, sigma, inv_tau;
+    double norm_A, norm_Q;
+    // inner tolerance (Section 3.3)
+    double eps;
+    double gamma_inner, eps_min, eps_fixed;
+    // MPRGP state
+    double abar, abar_scale, mprgp_gamma;
+    double alpha, gam, pHp;
+    double gp2, b2, ptp;           // ||g^P||^2, ||beta||^2, phit'phi at the current x
+    double res;                    // ||g^P|| at the last decision
+    long long inner_it, inner_total, max_inner;
+    int done, need_g, skip_update, dir_mode, last_step, step_kind, proportional, pad0;
+    // outer state (Sections 3.1-3.2)
+    long long k, t, restarts, checks, max_iter;
+    double theta;
+    int use_halpern, store_delta, restart_pending, pad1;
+    double ndx2, ndy2;             // ||x_T - x^k||^2, ||y_T - y^k||^2 of the last iteration
+    double R_start, R_prev;
+    int R_prev_valid, status, has_unbounded_x, pad2;
+    double kp, ki, kd, pid_int, pid_prev;
+    double rs_suff, rs_nec, rs_art;
+    double tol, eps_inf;
+    // check results (Section 4, 5)
+    double pviol, py_sum, mvy2;            // A x_T side
+    double dviol, qx_max, aty_max, c_max, xqx, cx, pr_sum, natural, mvx2;
+    double r_primal, r_dual, r_gap, pobj, dobj;
+    double bscale_p;                        // 1 + max(||lc||, ||uc||) over finite entries
+    double ytil_max, ptil_sum, ptil_abs;    // primal-infeasibility pieces
+    double w_viol, pw_sum, pw_abs;
+    double d_max, cd, ad_viol, qd_max, gamma_q;
+    int pinf, dinf, pad3, pad4;
+    // power iteration
+    double pw_norm;
+};
+
+struct DevState {
+    int n = 0, m = 0;
+    CsrDev Q, A, AT;
+    int qdiag = 0;                 // Q diagonal (closed-form primal step)
+    double* qd = nullptr;          // diagonal of Q (n)
+    double *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
+    // iterates
+    double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
+    // work vectors
+    double *rhs = nullptr, *g = nullptr, *p = nullptr, *hp = nullptr, *aty = nullptr;
+    double *dx = nullptr, *ytil = nullptr, *v1 = nullptr, *v2 = nullptr;
+    Ctrl* ctrl = nullptr;
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    unsigned long long* dstat = nullptr;   // pinned status word (device view)
+    unsigned long long* dcheck = nullptr;  // pinned check result (device view)
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+// Every launcher enqueues on `s` and returns hipGetLastError().
+hipError_t launch_init_start(const DevState& S, hipStream_t s);
+hipError_t launch_prox_diag(const DevState& S, hipStream_t s);
+hipError_t launch_rhs(const DevState& S, hipStream_t s);
+hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
+hipError_t launch_dir(const DevState& S, hipStream_t s);
+hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s);
+hipError_t launch_update(const DevState& S, long long seq, hipStream_t s);
+hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s);
+hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s);
+// KKT pieces at (x, y); with `full` also the infeasibility certificates
+// (and, with `dinf`, the unboundedness ones) and the solver's decision
+hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
+                        hipStream_t s);
+hipError_t launch_restart_copy(const DevState& S, hipStream_t s);
+// power iteration pieces: v <- unit start vector; w = M v with ||w||^2; v = w / ||w||
+hipError_t launch_power_start(const DevState& S, double* v, int len, hipStream_t s);
+hipError_t launch_spmv_norm(const DevState& S, const CsrDev& M, const double* x, double* y,
+                            hipStream_t s);
+hipError_t launch_scale(const DevState& S, double* v, int len, hipStream_t s);
+// operator-level entry points
+hipError_t launch_spmv_plain(const DevState& S, const CsrDev& M, const double* x, double* y,
+                             hipStream_t s);
+hipError_t launch_dot(const DevState& S, const double* a, const double* b, int len,
+                      hipStream_t s);
+
+int vec_grid(long long len);
+
+}  // namespace pdhcg

@@ -1,0 +1,157 @@
+"""C-ABI checks that need no GPU: the library loads and exports every
+function include/pdhcg.h declares, parameters default to the paper's
+constants, input validation rejects malformed problems before touching a
+device, and the SpMV schedule covers every nonzero exactly once."""
+
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2602_23967_amd as P
+from paper_2602_23967_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdhcg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_params_default_paper_constants():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
+    p = P.qp_params_default()
+    assert p.gamma_inner == g["gamma_inner"]["value"]
+    assert p.eps_min == g["eps_min"]["value"]
+    assert p.eta_scale == g["eta_scale"]["value"]
+    assert p.tol == g["tol"]["value"]
+
+
+def _bad(fn, code):
+    with pytest.raises(P.QPError) as e:
+        fn()
+    assert e.value.code == code
+    assert P.qp_last_error() != ""
+
+
+def test_validation_errors():
+    q = I.tiny(0, n=5, m=3)
+    mk = lambda **kw: (lambda: P.qp_create(kw.get("n", q.n), kw.get("m", q.m), kw.get("Q", q.Q),
+                                           kw.get("A", q.A), kw.get("c", q.c), kw.get("b", q.b),
+                                           kw.get("sense", q.sense), kw.get("lb", q.lb),
+                                           kw.get("ub", q.ub)))
+    _bad(mk(n=0), P.ERR_INVALID_ARG)
+    _bad(mk(lb=q.ub, ub=q.lb - 1.0), P.ERR_INVALID_ARG)                 # lb > ub
+    _bad(mk(lb=np.full(q.n, np.inf)), P.ERR_INVALID_ARG)                # lb = +inf
+    c = q.c.copy(); c[2] = np.nan
+    _bad(mk(c=c), P.ERR_INVALID_ARG)
+    b = q.b.copy(); b[0] = np.inf
+    _bad(mk(b=b), P.ERR_INVALID_ARG)
+    _bad(mk(sense=b"EXG"), P.ERR_INVALID_ARG)
+    Qn = q.Q.toarray(); Qn[0, 1] += 1.0
+    _bad(mk(Q=sp.csr_matrix(Qn)), P.ERR_NOT_SYMMETRIC)
+    Qp = q.Q.toarray(); Qp[0, 4] = 0.0; Qp[4, 0] = 0.0
+    Qs = sp.csr_matrix(Qp); Qs.eliminate_zeros()
+    Qs = Qs.tolil(); Qs[0, 4] = 1.0; Qs = Qs.tocsr()
+    _bad(mk(Q=Qs), P.ERR_NOT_SYMMETRIC)
+
+
+def test_validation_raw_csr_errors():
+    """Raw CSR arrays that scipy would normalise: unsorted / duplicate /
+    out-of-range columns, decreasing row pointers, non-finite values."""
+    import ctypes as C
+    L = P.lib()
+    n, m = 3, 2
+    c = np.zeros(n)
+    b = np.zeros(m)
+    def call(ap, aj, av):
+        ap = np.asarray(ap, np.int64); aj = np.asarray(aj, np.int32); av = np.asarray(av, np.float64)
+        h = C.c_void_p()
+        return L.qp_create(n, m, None, None, None, ap.ctypes.data_as(P._lp), aj.ctypes.data_as(P._ip),
+                           av.ctypes.data_as(P._dp), c.ctypes.data_as(P._dp), b.ctypes.data_as(P._dp),
+                           b"EE", None, None, C.byref(h))
+    assert call([0, 2, 3], [1, 0, 2], [1, 1, 1]) == P.ERR_INVALID_ARG      # unsorted
+    assert call([0, 2, 3], [1, 1, 2], [1, 1, 1]) == P.ERR_INVALID_ARG      # duplicate
+    assert call([0, 2, 3], [0, 3, 2], [1, 1, 1]) == P.ERR_INVALID_ARG      # out of range
+    assert call([0, 2, 1], [0, 1, 2], [1, 1, 1]) == P.ERR_INVALID_ARG      # decreasing
+    assert call([1, 2, 3], [0, 1, 2], [1, 1, 1]) == P.ERR_INVALID_ARG      # rowptr[0] != 0
+    assert call([0, 2, 3], [0, 1, 2], [1, np.nan, 1]) == P.ERR_INVALID_ARG
+    assert call([0, 2, 3], [0, 1, 2], [1, np.inf, 1]) == P.ERR_INVALID_ARG
+
+
+def test_ranged_validation():
+    q = I.tiny(1, n=4, m=2)
+    _bad(lambda: P.qp_create_ranged(q.n, q.m, q.Q, q.A, q.c, np.array([1.0, 0.0]),
+                                    np.array([0.0, 1.0]), q.lb, q.ub), P.ERR_INVALID_ARG)
+    _bad(lambda: P.qp_create_ranged(q.n, q.m, q.Q, q.A, q.c, np.array([np.inf, 0.0]),
+                                    np.array([np.inf, 1.0]), q.lb, q.ub), P.ERR_INVALID_ARG)
+
+
+def test_null_handle_calls():
+    import ctypes as C
+    L = P.lib()
+    assert L.qp_solve(None, 1e-6, 10) == P.ERR_INVALID_ARG
+    assert L.qp_result(None, None, None, None) == P.ERR_INVALID_ARG
+    assert L.qp_set_stream(None, None) == P.ERR_INVALID_ARG
+    L.qp_destroy(None)
+
+
+@pytest.mark.parametrize("lengths", [
+    [11] * 1000,                                   # short uniform rows
+    [0, 0, 3, 0, 5000, 1, 2048, 2049, 0, 7] * 3,   # empty, long and boundary rows
+    [1] * 300 + [300] * 20 + [4097] + [0] * 5,     # row cap, medium rows, a long row
+    [],                                            # no rows
+    [0] * 10,                                      # only empty rows
+])
+def test_spmv_schedule_covers_each_nonzero_once(lengths):
+    rp = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    items = P.qp_spmv_schedule(rp)
+    rows = len(lengths)
+    seen_rows = np.zeros(rows, int)
+    seen_nnz = np.zeros(int(rp[-1]), int)
+    seg_slots = set()
+    for row0, nr, k0, k1, lr, seg, nseg, base in items:
+        assert 0 <= k1 - k0 <= 2048
+        if nr > 0:
+            assert nr <= 256
+            assert k0 == rp[row0] and k1 == rp[row0 + nr]
+            seen_rows[row0:row0 + nr] += 1
+            seen_nnz[k0:k1] += 1
+        elif nseg > 0:
+            assert lengths[row0] > 2048 and 0 <= seg < nseg
+            assert rp[row0] <= k0 < k1 <= rp[row0 + 1]
+            seen_nnz[k0:k1] += 1
+            seg_slots.add(base + seg)
+            if seg == 0:
+                seen_rows[row0] += 1
+        else:
+            assert k0 == k1
+    assert np.all(seen_rows == 1)
+    assert np.all(seen_nnz == 1)
+    assert seg_slots == set(range(len(seg_slots)))
+
+
+def test_no_device_gives_device_error_or_success():
+    """On a machine without a GPU, a valid problem passes validation and
+    fails only at the device step; with a GPU it is created."""
+    q = I.tiny(2, n=4, m=2)
+    try:
+        h = P.qp_create_from(q)
+    except P.QPError as e:
+        assert e.code == P.ERR_DEVICE
+    else:
+        P.qp_destroy(h)
