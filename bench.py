@@ -90,7 +90,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--timing", type=int, default=4, help="time every k-th launch per kernel family")
+    ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
+    ap.add_argument("--max-iter", type=int, default=100000,
+                    help="outer iteration cap (lower only for short profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device copies of 64 MiB (scale for rocprofv3 byte counters)")
     ap.add_argument("--cpu-sample-iters", type=int, default=8)
     args = ap.parse_args()
 
@@ -100,6 +105,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        src = torch.zeros(8 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 copies of 67108864 bytes each way")
+        return
 
     import paper_2602_23967_amd as P
     from paper_2602_23967_amd import instances as I
@@ -112,7 +126,8 @@ def main():
     log(f"generated {q.name}: n={q.n} m={q.m} nnz(Q)={q.nnz_Q} nnz(A)={q.nnz_A} "
         f"in {time.perf_counter() - t:.1f}s")
     h = P.qp_create_from(q)
-    params = P.qp_params_default(tol=args.tol, timing=args.timing)
+    params = P.qp_params_default(tol=args.tol, timing=args.timing, inner_lag=args.lag,
+                                 max_iter=args.max_iter)
     try:
         for w in range(args.warmup):
             st = P.qp_solve_ex(h, params)

@@ -69,7 +69,7 @@ typedef struct {
     int64_t check_every;      /* cadence of KKT / infeasibility / restart checks; 64 */
     int64_t max_inner;        /* cap on inner iterations per subproblem; 500 */
     int use_halpern;          /* 1: reflected Halpern averaging (Section 3.1); 0: plain PDHG */
-    int inner_lag;            /* inner steps queued ahead of the host's view of the stop flag; 2 */
+    int inner_lag;            /* inner steps queued ahead of the host's view of the stop flag; 1 */
     double theta;             /* Halpern reflection; 1 */
     double kp, ki, kd;        /* PID gains on log(omega) (Section 3.2); 0.99, 0.01, 0 */
     double gamma_inner;       /* (paper, Section 3.3) 5e-4 */

@@ -164,8 +164,73 @@ void build_plan(int64_t rows, const int64_t* rp, std::vector<BlkDesc>& blk, int&
     if (blk.empty()) blk.push_back({0, 0, 0, 0, 0, 0, 0, 0});
 }
 
+// Column-partitioned layout (see pdhcg_internal.h): part p holds the entries
+// of columns [p*w, (p+1)*w), w = ceil(cols / NPARTS), stored part after part
+// with absolute row pointers; each part gets row blocks of <= NNZ_CAP
+// nonzeros and <= PART_ROWS_CAP rows, and the blocks are interleaved so that
+// block b belongs to part b % NPARTS.  Returns false (no partitioning) when a
+// row of a part exceeds NNZ_CAP.
+bool build_parts(int64_t rows, int64_t cols, const int64_t* rp, const int32_t* cj, const double* v,
+                 std::vector<int>& prow, std::vector<int32_t>& pcol, std::vector<double>& pval,
+                 std::vector<BlkDesc>& blk)
+{
+    const int64_t w = (cols + NPARTS - 1) / NPARTS;
+    const int64_t nnz = rp[rows];
+    // per (row, part) counts
+    std::vector<int64_t> cnt((size_t)NPARTS * rows, 0);
+    for (int64_t i = 0; i < rows; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) cnt[(size_t)(cj[k] / w) * rows + i]++;
+    for (size_t q = 0; q < cnt.size(); ++q)
+        if (cnt[q] > NNZ_CAP) return false;
+    prow.assign((size_t)NPARTS * (rows + 1), 0);
+    int64_t off = 0;
+    for (int p = 0; p < NPARTS; ++p) {
+        int* pr = prow.data() + (size_t)p * (rows + 1);
+        pr[0] = (int)off;
+        for (int64_t i = 0; i < rows; ++i) {
+            off += cnt[(size_t)p * rows + i];
+            pr[i + 1] = (int)off;
+        }
+    }
+    pcol.resize(nnz);
+    pval.resize(nnz);
+    std::vector<int64_t> fill(NPARTS);
+    for (int64_t i = 0; i < rows; ++i) {
+        for (int p = 0; p < NPARTS; ++p) fill[p] = prow[(size_t)p * (rows + 1) + i];
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int p = (int)(cj[k] / w);
+            pcol[fill[p]] = cj[k];
+            pval[fill[p]] = v[k];
+            ++fill[p];
+        }
+    }
+    std::vector<std::vector<BlkDesc>> per(NPARTS);
+    size_t nb = 0;
+    for (int p = 0; p < NPARTS; ++p) {
+        const int* pr = prow.data() + (size_t)p * (rows + 1);
+        int64_t r = 0;
+        while (r < rows) {
+            const int64_t start = r;
+            int64_t z = 0;
+            while (r < rows && r - start < PART_ROWS_CAP) {
+                const int64_t L = pr[r + 1] - pr[r];
+                if (z + L > NNZ_CAP) break;
+                z += L;
+                ++r;
+            }
+            per[p].push_back({(int)start, (int)(r - start), pr[start], pr[r], p, 0, 0, 0});
+        }
+        nb = std::max(nb, per[p].size());
+    }
+    blk.clear();
+    for (size_t i = 0; i < nb; ++i)
+        for (int p = 0; p < NPARTS; ++p)
+            blk.push_back(i < per[p].size() ? per[p][i] : BlkDesc{0, 0, 0, 0, p, 0, 0, 0});
+    return true;
+}
+
 struct EventPair {
-    hipEvent_t a, b;
+    hipEvent_t ev[2];   // around the main kernel of one launch (not its finishing kernel)
     int fam;
 };
 
@@ -229,6 +294,26 @@ int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_
     M.rows = (int)rows;
     M.cols = (int)cols;
     M.nnz = rp ? rp[rows] : 0;
+    if (rp && cols >= PART_MIN_COLS && rows > 0 && M.nnz > 0) {
+        std::vector<int> prow;
+        std::vector<int32_t> pcol;
+        std::vector<double> pval;
+        std::vector<BlkDesc> blk;
+        if (build_parts(rows, cols, rp, cj, v, prow, pcol, pval, blk)) {
+            int rc;
+            M.nparts = NPARTS;
+            M.nblk = (int)blk.size();
+            if ((rc = upload(h, &M.rowptr, prow.data(), prow.size()))) return rc;
+            if ((rc = upload(h, &M.col, pcol.data(), pcol.size()))) return rc;
+            if ((rc = upload(h, &M.val, pval.data(), pval.size()))) return rc;
+            if ((rc = upload(h, &M.blk, blk.data(), blk.size()))) return rc;
+            if ((rc = dalloc(h, &M.ypart, (size_t)NPARTS * rows))) return rc;
+            if ((rc = dalloc(h, &M.seg_part, 1))) return rc;
+            if ((rc = dalloc(h, &M.lr_info, 1))) return rc;
+            M.nlr = 0;
+            return 0;
+        }
+    }
     std::vector<int> rp32(rows + 1, 0);
     for (int64_t i = 0; i <= rows; ++i) rp32[i] = rp ? (int)rp[i] : 0;
     int rc;
@@ -243,8 +328,15 @@ int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_
     M.nblk = (int)blk.size();
     if ((rc = upload(h, &M.blk, blk.data(), blk.size()))) return rc;
     if ((rc = dalloc(h, &M.seg_part, (size_t)std::max(nseg, 1)))) return rc;
-    if ((rc = dalloc(h, &M.lr_count, (size_t)std::max(nlr, 1)))) return rc;
-    HIPCHK(hipMemset(M.lr_count, 0, sizeof(unsigned) * std::max(nlr, 1)));
+    std::vector<int> info;
+    for (const BlkDesc& b : blk)
+        if (b.nrows == 0 && b.nseg > 0 && b.seg == 0) {
+            info.push_back(b.row0);
+            info.push_back(b.seg_base);
+            info.push_back(b.nseg);
+        }
+    M.nlr = nlr;
+    if ((rc = upload(h, &M.lr_info, info.data(), info.size()))) return rc;
     return 0;
 }
 
@@ -365,7 +457,7 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if ((rc = upload(h, &S.uv, uvv.data(), n))) return bail(rc);
     if ((rc = upload(h, &S.lc, lcv.data(), m))) return bail(rc);
     if ((rc = upload(h, &S.uc, ucv.data(), m))) return bail(rc);
-    double** nvecs[] = {&S.x, &S.xa, &S.xt, &S.rhs, &S.g, &S.p, &S.hp, &S.aty, &S.dx};
+    double** nvecs[] = {&S.x, &S.xa, &S.xt, &S.rhs, &S.g, &S.p, &S.hp, &S.aty, &S.dx, &S.xbar};
     for (double** pv : nvecs)
         if ((rc = dalloc(h, pv, n))) return bail(rc);
     double** mvecs[] = {&S.y, &S.ya, &S.yt, &S.ytil};
@@ -375,11 +467,9 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if ((rc = dalloc(h, &S.v1, nm))) return bail(rc);
     if ((rc = dalloc(h, &S.v2, nm))) return bail(rc);
     if ((rc = dalloc(h, &S.ctrl, 1))) return bail(rc);
-    const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, VEC_GRID_MAX});
+    const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, VEC_GRID_MAX});   // partials slots
     if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8))) return bail(rc);
-    if ((rc = dalloc(h, &S.counter, 1))) return bail(rc);
-    if (hipMemset(S.counter, 0, sizeof(unsigned)) != hipSuccess ||
-        hipMemset(S.ctrl, 0, sizeof(Ctrl)) != hipSuccess)
+    if (hipMemset(S.ctrl, 0, sizeof(Ctrl)) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemset failed"));
 
     // scalars of the problem
@@ -435,16 +525,14 @@ struct Timed {
     Timed(qp_handle* hh, int f) : h(hh), fam(f)
     {
         const int64_t k = h->fam_launches[fam]++;
-        if (h->timing > 0 && k % h->timing == 0 && h->ev_used < h->ev_pool.size()) {
+        if (h->timing > 0 && fam != QP_FAM_CHECK && k % h->timing == 0 &&
+            h->ev_used < h->ev_pool.size()) {
             ev = &h->ev_pool[h->ev_used++];
             ev->fam = fam;
-            (void)hipEventRecord(ev->a, h->stream);
+            h->S.tev = ev->ev;
         }
     }
-    ~Timed()
-    {
-        if (ev) (void)hipEventRecord(ev->b, h->stream);
-    }
+    ~Timed() { h->S.tev = nullptr; }
 };
 
 void setup_ctrl(qp_handle* h, const qp_params& p, Ctrl& c)
@@ -484,14 +572,19 @@ void setup_ctrl(qp_handle* h, const qp_params& p, Ctrl& c)
 // Runs one inner solve (gradient at the warm start, then steps until the
 // device posts "done").  The host keeps `lag` steps queued beyond the last
 // status it has seen, so the GPU never waits for the host.
-int inner_solve(qp_handle* h, long long& gseq, int lag)
+// `exact`: form rhs (already done by the caller) and the gradient with a
+// product with Q; otherwise update both from the previous subproblem.
+int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact)
 {
     DevState& S = h->S;
     hipStream_t s = h->stream;
     const long long base = gseq;
-    {
+    if (exact) {
         Timed t(h, QP_FAM_GINIT);
         HIPCHK(launch_ginit(S, base, s));
+    } else {
+        Timed t(h, QP_FAM_RHS);
+        HIPCHK(launch_rhs_grad(S, base, s));
     }
     volatile unsigned long long* word = h->hstat;
     long long issued = 0;
@@ -553,7 +646,7 @@ qp_params qp_params_default(void)
     p.check_every = 64;
     p.max_inner = 500;
     p.use_halpern = 1;
-    p.inner_lag = 2;
+    p.inner_lag = 1;
     p.theta = 1.0;
     p.kp = 0.99;
     p.ki = 0.01;
@@ -633,8 +726,8 @@ void qp_destroy(qp_handle* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (void* p : h->dev_allocs) (void)hipFree(p);
     for (EventPair& e : h->ev_pool) {
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.ev[0]);
+        (void)hipEventDestroy(e.ev[1]);
     }
     if (h->hstat) (void)hipHostFree(h->hstat);
     if (h->own) (void)hipStreamDestroy(h->own);
@@ -665,8 +758,8 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     if (p.timing > 0 && h->ev_pool.empty()) {
         h->ev_pool.resize(4096);
         for (EventPair& e : h->ev_pool) {
-            HIPCHK(hipEventCreate(&e.a));
-            HIPCHK(hipEventCreate(&e.b));
+            HIPCHK(hipEventCreate(&e.ev[0]));
+            HIPCHK(hipEventCreate(&e.ev[1]));
         }
     }
 
@@ -707,12 +800,17 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
             Timed t(h, QP_FAM_RHS);
             HIPCHK(launch_prox_diag(S, s));
         } else {
-            {
+            // the gradient is formed with a product with Q at the first
+            // iteration and after every check (bounds the drift of the
+            // recurrence to check_every iterations); otherwise it is updated
+            const bool exact = (k % p.check_every == 0);
+            if (exact) {
                 Timed t(h, QP_FAM_RHS);
                 HIPCHK(launch_rhs(S, s));
             }
-            int rc = inner_solve(h, gseq, p.inner_lag);
+            int rc = inner_solve(h, gseq, p.inner_lag, exact);
             if (rc) return rc;
+            HIPCHK(launch_xbar(S, s));
         }
         {
             Timed t(h, QP_FAM_DUAL);
@@ -752,7 +850,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     for (int f = 0; f < QP_NFAM; ++f) I.fam_launches[f] = h->fam_launches[f];
     for (size_t i = 0; i < h->ev_used; ++i) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, h->ev_pool[i].a, h->ev_pool[i].b) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, h->ev_pool[i].ev[0], h->ev_pool[i].ev[1]) == hipSuccess) {
             I.fam_ms[h->ev_pool[i].fam] += ms;
             I.fam_timed[h->ev_pool[i].fam] += 1;
         }
@@ -830,10 +928,11 @@ int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double
     HIPCHK(hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(S.rhs, rhs, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(S.xt, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_clip(S, S.xt, s));
     HIPCHK(hipStreamSynchronize(s));
     h->hstat[0] = 0;
     long long gseq = 1;
-    int rc = inner_solve(h, gseq, 2);
+    int rc = inner_solve(h, gseq, 2, true);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -6,15 +6,18 @@
 //              indices, then sums each row with a lane group sized to the
 //              block's row count (1..64 lanes, wavefront shuffles), and hands
 //              the row sum to the fused epilogue E.  Rows longer than NNZ_CAP
-//              are split into segments whose partial sums are combined, in
-//              segment order, by the last segment block to arrive.
+//              are split into segments; each segment block stores its partial
+//              sum and the finishing kernel completes the row in segment order.
 //   k_vec<E>   grid-stride elementwise pass with epilogue E.
-// Both finish with a deterministic two-level reduction of up to 8 scalars
-// (wavefront xor-shuffle tree, then LDS across the block's 4 waves, then the
-// per-block partials summed in block order by the last block to arrive),
-// whose last block runs E::finalize: the scalar control logic of the method
-// (step lengths, inner-solver branch, tolerance, restart, PID, status).
-// No floating-point atomics are used, so every result is reproducible.
+// A kernel whose epilogue reduces scalars stores one partial per block
+// (wavefront xor-shuffle tree, then LDS across the block's 4 waves), and a
+// one-block finishing kernel (k_spmv_fin / k_vec_fin) sums the partials in
+// block order and runs E::finalize: the scalar control logic of the method
+// (step lengths, inner-solver branch, tolerance, restart, PID, status).  The
+// kernel boundary is the only grid-wide synchronisation: no device-scope
+// fences or atomics (on gfx950 an agent-scope release writes back the XCD's
+// L2, which thousands of blocks cannot afford), and no floating-point
+// atomics, so every result is reproducible.
 #include <math.h>
 
 #include "pdhcg_internal.h"
@@ -35,24 +38,12 @@ __device__ __forceinline__ double rcomb(int kind, double a, double b)
 // identities: every MAX slot reduces magnitudes, so 0 is its identity
 __device__ __forceinline__ double rid(int kind) { return kind == R_MIN ? INFINITY : 0.0; }
 
-__device__ __forceinline__ void st_agent(double* p, double v)
-{
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
-                       static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double ld_agent(const double* p)
-{
-    return __longlong_as_double(static_cast<long long>(__hip_atomic_load(
-        reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-}
-
+// status word in pinned host memory: a single 64-bit store (no fence; the
+// host only needs it eventually, and the kernel's end publishes it anyway)
 __device__ __forceinline__ void post_status(unsigned long long* w, long long seq, int flag)
 {
     __hip_atomic_store(w, (static_cast<unsigned long long>(seq) << 1) | (flag ? 1ull : 0ull),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __threadfence_system();
 }
 
 __device__ __forceinline__ double clampd(double v, double l, double u)
@@ -124,7 +115,7 @@ __device__ __forceinline__ Split split(double x, double g, double l, double u, d
 // reductions
 // ---------------------------------------------------------------------------
 
-template <class E>
+template <class E, int NT = TPB>
 __device__ __forceinline__ void block_reduce(double (&v)[E::NR > 0 ? E::NR : 1], double* lds)
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
@@ -143,47 +134,11 @@ __device__ __forceinline__ void block_reduce(double (&v)[E::NR > 0 ? E::NR : 1],
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             double r = lds[j];
-            for (int w = 1; w < TPB / 64; ++w) r = rcomb(E::kind(j), r, lds[w * NR + j]);
+            for (int w = 1; w < NT / 64; ++w) r = rcomb(E::kind(j), r, lds[w * NR + j]);
             v[j] = r;
         }
     }
     __syncthreads();
-}
-
-// Publishes the block's partials; returns true in the last block to arrive,
-// which then holds the grid totals in `tot`.
-template <class E>
-__device__ bool publish(double (&v)[E::NR > 0 ? E::NR : 1], double* partials, unsigned* counter,
-                        double* lds, double* tot)
-{
-    constexpr int NR = E::NR > 0 ? E::NR : 1;
-    __shared__ int s_last;
-    block_reduce<E>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NR; ++j) st_agent(&partials[(size_t)blockIdx.x * NR + j], v[j]);
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        s_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    double r[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) r[j] = rid(E::kind(j));
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += TPB) {
-#pragma unroll
-        for (int j = 0; j < NR; ++j) r[j] = rcomb(E::kind(j), r[j], ld_agent(&partials[(size_t)b * NR + j]));
-    }
-    block_reduce<E>(r, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NR; ++j) tot[j] = r[j];
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    return true;
 }
 
 struct SumOne {
@@ -196,13 +151,12 @@ struct SumOne {
 // ---------------------------------------------------------------------------
 
 template <class E>
-__global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials, unsigned* counter)
+__global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double prod[NNZ_CAP];
+    __shared__ int srp[PART_ROWS_CAP + 1];   // the block's row pointers, relative to k0
     __shared__ double lds[NR * (TPB / 64)];
-    __shared__ double tot[NR];
-    __shared__ int s_seg_last;
     E e = epi;
     if (e.skip()) return;
     e.init();
@@ -212,6 +166,10 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials,
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
 
     const int cnt = d.k1 - d.k0;
+    if (d.nrows > 0) {
+        const int* rp = M.rowptr + (size_t)d.lr * (M.rows + 1) + d.row0;
+        for (int r = threadIdx.x; r <= d.nrows; r += TPB) srp[r] = rp[r] - d.k0;
+    }
     {
         int cj[NNZ_CAP / TPB];
         double av[NNZ_CAP / TPB];
@@ -233,44 +191,98 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials,
         int G = 64;
         while (G > 1 && G * d.nrows > TPB) G >>= 1;
         const int grp = threadIdx.x / G, lane = threadIdx.x - grp * G;
-        if (grp < d.nrows) {
-            const int row = d.row0 + grp;
-            const int a = M.rowptr[row] - d.k0, b = M.rowptr[row + 1] - d.k0;
+        const bool partial = M.nparts > 1;
+        for (int r = grp; r < d.nrows; r += TPB / G) {
+            const int row = d.row0 + r;
+            const int a = srp[r], b = srp[r + 1];
             double s = 0.0;
             for (int i = a + lane; i < b; i += G) s += prod[i];
             for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
-            if (lane == 0) e.row(row, s, acc);
+            if (lane == 0) {
+                if (partial) M.ypart[(size_t)d.lr * M.rows + row] = s;
+                else e.row(row, s, acc);
+            }
         }
     } else if (d.nseg > 0) {
         double s[1] = {0.0};
         for (int q = threadIdx.x; q < cnt; q += TPB) s[0] += prod[q];
         block_reduce<SumOne>(s, lds);
-        if (threadIdx.x == 0) {
-            st_agent(&M.seg_part[d.seg_base + d.seg], s[0]);
-            __threadfence();
-            const unsigned prev = atomicAdd(&M.lr_count[d.lr], 1u);
-            s_seg_last = prev == (unsigned)(d.nseg - 1);
-        }
-        __syncthreads();
-        if (s_seg_last && threadIdx.x == 0) {
-            __threadfence();
-            double total = 0.0;
-            for (int i = 0; i < d.nseg; ++i) total += ld_agent(&M.seg_part[d.seg_base + i]);
-            __hip_atomic_store(&M.lr_count[d.lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            e.row(d.row0, total, acc);
-        }
+        if (threadIdx.x == 0) M.seg_part[d.seg_base + d.seg] = s[0];
     }
     if constexpr (E::NR > 0) {
-        if (publish<E>(acc, partials, counter, lds, tot) && threadIdx.x == 0) e.finalize(tot);
+        if (M.nparts > 1) return;   // the row pass reduces
+        block_reduce<E>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) partials[(size_t)blockIdx.x * NR + j] = acc[j];
+        }
+    }
+}
+
+// row pass of a column-partitioned product: y_i = sum over parts (in part
+// order) of the partial row sums, handed to the epilogue
+template <class E>
+__global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double lds[NR * (TPB / 64)];
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+    const long long stride = (long long)gridDim.x * TPB;
+    for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < M.rows; i += stride) {
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < NPARTS; ++p) s += M.ypart[(size_t)p * M.rows + i];
+        e.row((int)i, s, acc);
+    }
+    if constexpr (E::NR > 0) {
+        block_reduce<E>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) partials[(size_t)blockIdx.x * NR + j] = acc[j];
+        }
+    }
+}
+
+// one block: completes the long rows (segment sums in segment order), sums
+// the per-block partials in block order, and runs the epilogue's finalize
+template <class E>
+__global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const double* partials)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double lds[NR * (FIN_T / 64)];
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+    for (int lr = threadIdx.x; lr < M.nlr; lr += FIN_T) {
+        const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
+        double total = 0.0;
+        for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
+        e.row(row, total, acc);
+    }
+    if constexpr (E::NR > 0) {
+#pragma unroll 4
+        for (int b = threadIdx.x; b < M.nblk; b += FIN_T) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) acc[j] = rcomb(E::kind(j), acc[j], partials[(size_t)b * NR + j]);
+        }
+        block_reduce<E, FIN_T>(acc, lds);
+        if (threadIdx.x == 0) e.finalize(acc);
     }
 }
 
 template <class E>
-__global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* partials, unsigned* counter)
+__global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* partials)
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double lds[NR * (TPB / 64)];
-    __shared__ double tot[NR];
     E e = epi;
     if (e.skip()) return;
     e.init();
@@ -280,8 +292,32 @@ __global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* parti
     const long long stride = (long long)gridDim.x * TPB;
     for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < len; i += stride) e.elem(i, acc);
     if constexpr (E::NR > 0) {
-        if (publish<E>(acc, partials, counter, lds, tot) && threadIdx.x == 0) e.finalize(tot);
+        block_reduce<E>(acc, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) partials[(size_t)blockIdx.x * NR + j] = acc[j];
+        }
     }
+}
+
+template <class E>
+__global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double* partials)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double lds[NR * (FIN_T / 64)];
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nblk; b += FIN_T) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = rcomb(E::kind(j), acc[j], partials[(size_t)b * NR + j]);
+    }
+    block_reduce<E, FIN_T>(acc, lds);
+    if (threadIdx.x == 0) e.finalize(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,14 +356,33 @@ __device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long lo
 struct EpiProx : EpiBase {
     static constexpr int NR = 0;
     const double *y, *x, *c, *qd, *lv, *uv;
-    double* xt;
+    double *xt, *xbar;
     double it;
     __device__ void init() { it = ctrl->inv_tau; }
     __device__ double xval(int j) const { return y[j]; }
     __device__ void row(int i, double s, Acc<NR>) const
     {
-        xt[i] = clampd((x[i] * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
+        const double xi = x[i];
+        const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
+        xt[i] = v;
+        xbar[i] = 2.0 * v - xi;
     }
+};
+
+// extrapolated point x_bar = 2 x_T - x (eq. extrapolation)
+struct EpiXbar : EpiBase {
+    static constexpr int NR = 0;
+    const double *xt, *x;
+    double* xbar;
+    __device__ void elem(long long i, Acc<NR>) const { xbar[i] = 2.0 * xt[i] - x[i]; }
+};
+
+// x <- clip(x, l_v, u_v)
+struct EpiClip : EpiBase {
+    static constexpr int NR = 0;
+    const double *lv, *uv;
+    double* x;
+    __device__ void elem(long long i, Acc<NR>) const { x[i] = clampd(x[i], lv[i], uv[i]); }
 };
 
 // rhs of the primal subproblem (eq. primal_update): rhs = x/tau - c - A'y
@@ -341,22 +396,63 @@ struct EpiRhs : EpiBase {
     __device__ void row(int i, double s, Acc<NR>) const { rhs[i] = x[i] * it - c[i] - s; }
 };
 
-// gradient of the subproblem at the (clipped) warm start: g = Q x + x/tau - rhs,
+// rhs of the new subproblem and its gradient at the warm start x_T without a
+// product with Q: the previous subproblem ended with g = Q x_T + x_T/tau' - rhs'
+// (tau', rhs' its step and right-hand side), so the new gradient is
+// g + (rhs' - rhs) + x_T (1/tau - 1/tau'); split statistics as in EpiGinit
+struct EpiRhsGrad : EpiBase {
+    static constexpr int NR = 3;
+    const double *y, *x, *c, *xt, *lv, *uv;
+    double *rhs, *g;
+    unsigned long long* dstat;
+    long long seq;
+    double it, dit, abar;
+    __device__ void init()
+    {
+        it = ctrl->inv_tau;
+        dit = ctrl->inv_tau - ctrl->g_inv_tau;
+        abar = ctrl->abar;
+    }
+    __device__ double xval(int j) const { return y[j]; }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double r = x[i] * it - c[i] - s;
+        const double xi = xt[i];
+        const double gi = g[i] + (rhs[i] - r) + xi * dit;
+        rhs[i] = r;
+        g[i] = gi;
+        const Split sp = split(xi, gi, lv[i], uv[i], abar);
+        a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+        a[1] += sp.beta * sp.beta;
+        a[2] += sp.phit * sp.phi;
+    }
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* c = ctrl;
+        c->inner_it = 0;
+        c->last_step = STEP_NONE;
+        c->need_g = 0;
+        c->skip_update = 0;
+        c->g_inv_tau = c->inv_tau;
+        inner_decide(c, t[0], t[1], t[2], seq, dstat);
+    }
+};
+
+// gradient of the subproblem at the warm start (feasible): g = Q x + x/tau - rhs,
 // with split statistics; finalize starts the inner solve
 struct EpiGinit : EpiBase {
     static constexpr int NR = 3;
-    double* xt;
+    const double* xt;
     const double *rhs, *lv, *uv;
     double* g;
     unsigned long long* dstat;
     long long seq;
     double it, abar;
     __device__ void init() { it = ctrl->inv_tau; abar = ctrl->abar; }
-    __device__ double xval(int j) const { return clampd(xt[j], lv[j], uv[j]); }
+    __device__ double xval(int j) const { return xt[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
-        const double xi = clampd(xt[i], lv[i], uv[i]);
-        xt[i] = xi;
+        const double xi = xt[i];
         const double gi = s + it * xi - rhs[i];
         g[i] = gi;
         const Split sp = split(xi, gi, lv[i], uv[i], abar);
@@ -371,6 +467,7 @@ struct EpiGinit : EpiBase {
         c->last_step = STEP_NONE;
         c->need_g = 0;
         c->skip_update = 0;
+        c->g_inv_tau = c->inv_tau;
         if (isinf(c->eps) && c->eps_fixed <= 0.0) c->eps = fmax(c->gamma_inner * sqrt(t[0]), c->eps_min);
         inner_decide(c, t[0], t[1], t[2], seq, dstat);
     }
@@ -507,11 +604,11 @@ struct EpiDir : EpiBase {
     }
 };
 
-// dual step (eqs. extrapolation, dual_update) with x_bar = 2 x_T - x formed
-// on the fly, then the reflected Halpern average of y (Section 3.1)
+// dual step (eq. dual_update) on the extrapolated point x_bar = 2 x_T - x
+// (eq. extrapolation), then the reflected Halpern average of y (Section 3.1)
 struct EpiDual : EpiBase {
     static constexpr int NR = 4;
-    const double *xt, *x, *ya, *lc, *uc;
+    const double *xbar, *ya, *lc, *uc;
     double *y, *yt, *ytil;
     int store;
     double sigma, w, wa, th;
@@ -526,7 +623,7 @@ struct EpiDual : EpiBase {
         th = ctrl->theta;
         halpern = ctrl->use_halpern;
     }
-    __device__ double xval(int j) const { return 2.0 * xt[j] - x[j]; }
+    __device__ double xval(int j) const { return xbar[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
         const double yi = y[i], l = lc[i], u = uc[i];
@@ -906,14 +1003,30 @@ int vec_grid(long long len)
 template <class E>
 static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s)
 {
-    k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials, S.counter);
+    if (M.nparts > 1) {
+        const int grid = vec_grid(M.rows);
+        if (S.tev) (void)hipEventRecord(S.tev[0], s);
+        k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials);
+        k_rows<E><<<grid, TPB, 0, s>>>(M, e, S.partials);
+        if (S.tev) (void)hipEventRecord(S.tev[1], s);
+        if (E::NR > 0) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, S.partials);
+        return hipGetLastError();
+    }
+    if (S.tev) (void)hipEventRecord(S.tev[0], s);
+    k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials);
+    if (S.tev) (void)hipEventRecord(S.tev[1], s);
+    if (E::NR > 0 || M.nlr > 0) k_spmv_fin<E><<<1, FIN_T, 0, s>>>(M, e, S.partials);
     return hipGetLastError();
 }
 
 template <class E>
 static hipError_t run_vec(const DevState& S, long long len, const E& e, hipStream_t s)
 {
-    k_vec<E><<<vec_grid(len), TPB, 0, s>>>(len, e, S.partials, S.counter);
+    const int grid = vec_grid(len);
+    if (S.tev) (void)hipEventRecord(S.tev[0], s);
+    k_vec<E><<<grid, TPB, 0, s>>>(len, e, S.partials);
+    if (S.tev) (void)hipEventRecord(S.tev[1], s);
+    if (E::NR > 0) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, S.partials);
     return hipGetLastError();
 }
 
@@ -932,6 +1045,7 @@ hipError_t launch_prox_diag(const DevState& S, hipStream_t s)
     EpiProx e{};
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.qd = S.qd; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt;
+    e.xbar = S.xbar;
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -940,6 +1054,15 @@ hipError_t launch_rhs(const DevState& S, hipStream_t s)
     EpiRhs e{};
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.rhs = S.rhs;
+    return run_spmv(S, S.AT, e, s);
+}
+
+hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s)
+{
+    EpiRhsGrad e{};
+    e.ctrl = S.ctrl;
+    e.y = S.y; e.x = S.x; e.c = S.c; e.xt = S.xt; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.g = S.g;
+    e.dstat = S.dstat; e.seq = seq;
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -978,11 +1101,27 @@ hipError_t launch_update(const DevState& S, long long seq, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
+hipError_t launch_xbar(const DevState& S, hipStream_t s)
+{
+    EpiXbar e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.x = S.x; e.xbar = S.xbar;
+    return run_vec(S, S.n, e, s);
+}
+
+hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
+{
+    EpiClip e{};
+    e.ctrl = S.ctrl;
+    e.lv = S.lv; e.uv = S.uv; e.x = x;
+    return run_vec(S, S.n, e, s);
+}
+
 hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s)
 {
     EpiDual e{};
     e.ctrl = S.ctrl;
-    e.xt = S.xt; e.x = S.x; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
+    e.xbar = S.xbar; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
     return run_spmv(S, S.A, e, s);
 }

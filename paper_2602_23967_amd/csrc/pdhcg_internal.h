@@ -11,12 +11,24 @@ constexpr int TPB = 256;        // threads per block for every kernel
 constexpr int NNZ_CAP = 2048;   // nonzeros staged in LDS per row block
 constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at most)
 constexpr int VEC_GRID_MAX = 2048;
+// XCD-aware column partitioning: an operand larger than PART_MIN_COLS
+// doubles is split into NPARTS contiguous column parts; block b of the
+// product works on part b % NPARTS, which on gfx950's round-robin dispatch
+// keeps each XCD's gathers inside one part (1/8 of the operand, L2-resident)
+#ifndef PDHCG_NPARTS
+#define PDHCG_NPARTS 8
+#endif
+constexpr int NPARTS = PDHCG_NPARTS;
+constexpr int PART_MIN_COLS = 262144;
+constexpr int PART_ROWS_CAP = 1024;   // rows per block of a column part
+constexpr int FIN_T = 1024;     // threads of the one-block finishing kernels
 
 // One work item of the row-block SpMV schedule.
-//   nrows > 0            rows [row0, row0+nrows), nonzeros [k0, k1)
+//   nrows > 0            rows [row0, row0+nrows), nonzeros [k0, k1); for a
+//                        column-partitioned matrix `lr` is the column part
 //   nrows == 0, nseg > 0 segment `seg` of long row row0 (nonzeros [k0, k1));
-//                        partial sums land in seg_part[seg_base + seg] and the
-//                        last segment to arrive (counter lr) finishes the row
+//                        its partial sum lands in seg_part[seg_base + seg] and
+//                        the finishing kernel completes the row (long row lr)
 //   nrows == 0, nseg == 0 empty item (keeps a grid of >= 1 block)
 struct BlkDesc {
     int row0, nrows, k0, k1;
@@ -26,13 +38,16 @@ struct BlkDesc {
 struct CsrDev {
     int rows = 0, cols = 0;
     long long nnz = 0;
-    int* rowptr = nullptr;     // rows + 1
+    int nparts = 1;            // > 1: column-partitioned (part-major storage)
+    double* ypart = nullptr;   // nparts x rows partial row sums (partitioned only)
+    int* rowptr = nullptr;     // nparts x (rows + 1), absolute offsets
     int* col = nullptr;
     double* val = nullptr;
     BlkDesc* blk = nullptr;
     int nblk = 0;
     double* seg_part = nullptr;
-    unsigned* lr_count = nullptr;
+    int* lr_info = nullptr;    // per long row: {row, first segment slot, segment count}
+    int nlr = 0;
 };
 
 // inner-solver direction kinds
@@ -52,6 +67,7 @@ struct Ctrl {
     // MPRGP state
     double abar, abar_scale, mprgp_gamma;
     double alpha, gam, pHp;
+    double g_inv_tau;              // 1/tau of the subproblem the gradient g belongs to
     double gp2, b2, ptp;           // ||g^P||^2, ||beta||^2, phit'phi at the current x
     double res;                    // ||g^P|| at the last decision
     long long inner_it, inner_total, max_inner;
@@ -89,10 +105,10 @@ struct DevState {
     double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
     // work vectors
     double *rhs = nullptr, *g = nullptr, *p = nullptr, *hp = nullptr, *aty = nullptr;
-    double *dx = nullptr, *ytil = nullptr, *v1 = nullptr, *v2 = nullptr;
+    double *dx = nullptr, *ytil = nullptr, *v1 = nullptr, *v2 = nullptr, *xbar = nullptr;
     Ctrl* ctrl = nullptr;
     double* partials = nullptr;
-    unsigned* counter = nullptr;
+    hipEvent_t* tev = nullptr;             // when set: events around the next main kernel
     unsigned long long* dstat = nullptr;   // pinned status word (device view)
     unsigned long long* dcheck = nullptr;  // pinned check result (device view)
 };
@@ -103,9 +119,14 @@ hipError_t launch_init_start(const DevState& S, hipStream_t s);
 hipError_t launch_prox_diag(const DevState& S, hipStream_t s);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
+// rhs and warm-start gradient of the next subproblem from the previous one's
+// gradient (no product with Q); starts the inner solve like launch_ginit
+hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_dir(const DevState& S, hipStream_t s);
 hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_update(const DevState& S, long long seq, hipStream_t s);
+hipError_t launch_xbar(const DevState& S, hipStream_t s);          // x_bar = 2 x_T - x
+hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- proj_X(x)
 hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s);
 // KKT pieces at (x, y); with `full` also the infeasibility certificates

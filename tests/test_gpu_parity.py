@@ -92,6 +92,32 @@ def test_spmv_parity_ragged_rows(torch):
         P.qp_destroy(h)
 
 
+@pytest.mark.parametrize("longest", [9000, 40000])
+def test_spmv_parity_wide_partitioned(torch, longest):
+    """Operands wider than 262144 columns use the XCD-partitioned schedule;
+    a row with more than 2048 nonzeros inside one column part (longest =
+    40000) makes the library fall back to the unpartitioned schedule."""
+    rng = np.random.default_rng(longest)
+    n = 300_000
+    lengths = [0, 1, 5, 64, 257, 2047, 2049, 5000, longest, 0, 3] + list(rng.integers(0, 40, 2000))
+    rows, cols, vals = [], [], []
+    for i, L in enumerate(lengths):
+        cc = rng.choice(n, size=int(L), replace=False)
+        rows += [i] * int(L)
+        cols += list(cc)
+        vals += list(rng.normal(size=int(L)))
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(len(lengths), n))
+    A.sort_indices()
+    m = A.shape[0]
+    h = P.qp_create(n, m, None, A, np.ones(n), np.zeros(m), b"L" * m, -np.ones(n), np.ones(n))
+    try:
+        for rep in range(2):
+            _spmv_check(torch, h, P.OP_A, A, rng.normal(size=n))
+            _spmv_check(torch, h, P.OP_AT, A.T.tocsr(), rng.normal(size=m))
+    finally:
+        P.qp_destroy(h)
+
+
 @pytest.mark.parametrize("length", [0, 1, 257, 12345, 1_000_000])
 def test_dot_matches_fsum(torch, length):
     q = I.tiny(0, n=4, m=2)
