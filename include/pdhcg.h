@@ -201,6 +201,42 @@ int qp_kkt(qp_handle* h, const double* x, const double* y, double* out);
 /* ||A||_2 and ||Q||_2 estimates of qp_create (host outputs, may be NULL). */
 int qp_norms(const qp_handle* h, double* norm_A, double* norm_Q);
 
+/* ---- batched solve: many independent QPs in one persistent launch --------
+ *
+ * For many small QPs with a diagonal (or zero) Q -- the case where the
+ * primal step is the closed form of Section 2.2, e.g. linear MPC -- solved
+ * together.  The caller packs the instances block-diagonally: instance i
+ * owns variables [var_off[i], var_off[i+1]) and rows [row_off[i],
+ * row_off[i+1]); Q (n x n, diagonal entries only, or NULL) and A (m x n,
+ * every entry inside its instance's block) are CSR as in qp_create, as are
+ * c, b, sense, lb, ub over all instances.  Each instance runs the method of
+ * qp_solve with its own step sizes, restarts, weight and status; one
+ * workgroup solves one instance at a time, so an instance's result does not
+ * depend on which other instances share the launch.  Same ownership and
+ * error rules as qp_create. */
+typedef struct qp_batch qp_batch;
+
+int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_off,
+                    const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
+                    const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+                    const double* c, const double* b, const char* sense,
+                    const double* lb, const double* ub, qp_batch** out);
+
+/* Solve every instance (params as qp_solve_ex; NULL = defaults; inner-solver
+ * fields are unused).  Blocking.  Returns the number of OPTIMAL instances or
+ * a negative error code. */
+int qp_batch_solve(qp_batch* bt, const qp_params* params);
+
+/* Result of instance i (host buffers of its n_i and m_i entries, any may be
+ * NULL), with the conventions of qp_result.  Returns the instance status. */
+int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info* info);
+
+/* Statuses of all instances (host, count entries) and the last solve's wall
+ * time in seconds (may be NULL). */
+int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds);
+
+void qp_batch_destroy(qp_batch* bt);
+
 /* ---- host-only diagnostics (no device call) --------------------------- */
 
 /* The SpMV work schedule the library builds for a CSR with `rows` rows and

@@ -103,6 +103,13 @@ def lib():
         L.qp_norms.argtypes = [C.c_void_p, _dp, _dp]
         L.qp_spmv_schedule.argtypes = [_i64, _lp, _ip, _i64]
         L.qp_spmv_schedule.restype = _i64
+        L.qp_batch_create.argtypes = [_i64, _lp, _lp, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp,
+                                      C.c_char_p, _dp, _dp, C.POINTER(C.c_void_p)]
+        L.qp_batch_solve.argtypes = [C.c_void_p, C.POINTER(QPParams)]
+        L.qp_batch_result.argtypes = [C.c_void_p, _i64, _dp, _dp, C.POINTER(QPInfo)]
+        L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
+        L.qp_batch_destroy.argtypes = [C.c_void_p]
+        L.qp_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -281,6 +288,83 @@ class Solver:
 
     def close(self):
         qp_destroy(self.h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batched solve ----------------------------------------------------------------
+
+def qp_batch_create(count, var_off, row_off, Q, A, c, b, sense: bytes, lb=None, ub=None):
+    """Handle for `count` block-diagonally packed instances (see pdhcg.h)."""
+    vo = np.ascontiguousarray(var_off, dtype=np.int64)
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    qp_, qj_, qv_, keepq = _csr(Q)
+    ap_, aj_, av_, keepa = _csr(A) if A is not None else (None, None, None, ())
+    c, b, lb, ub = _f64(c), _f64(b), _f64(lb), _f64(ub)
+    h = C.c_void_p()
+    _check(lib().qp_batch_create(count, vo.ctypes.data_as(_lp), ro.ctypes.data_as(_lp), qp_, qj_,
+                                 qv_, ap_, aj_, av_, _d(c), _d(b), sense, _d(lb), _d(ub),
+                                 C.byref(h)))
+    return h
+
+
+def qp_batch_solve(h, params: QPParams | None = None) -> int:
+    return _check(lib().qp_batch_solve(h, None if params is None else C.byref(params)))
+
+
+def qp_batch_result(h, i, n_i, m_i):
+    x = np.zeros(n_i)
+    y = np.zeros(max(m_i, 1))
+    info = QPInfo()
+    st = _check(lib().qp_batch_result(h, i, _d(x), _d(y), C.byref(info)))
+    return st, x, y[:m_i], info.as_dict()
+
+
+def qp_batch_statuses(h, count):
+    st = np.zeros(count, dtype=np.int32)
+    sec = C.c_double(0.0)
+    _check(lib().qp_batch_statuses(h, st.ctypes.data_as(_ip), C.byref(sec)))
+    return st, sec.value
+
+
+def qp_batch_destroy(h):
+    if h is not None and h.value:
+        lib().qp_batch_destroy(h)
+        h.value = None
+
+
+class BatchSolver:
+    """Owns a batch of instances.QP objects (diagonal or zero Q each)."""
+
+    def __init__(self, qps):
+        from .instances import pack
+        self.qps = list(qps)
+        big, self.var_off, self.row_off = pack(self.qps)
+        self.h = qp_batch_create(len(self.qps), self.var_off, self.row_off, big.Q, big.A, big.c,
+                                 big.b, big.sense, big.lb, big.ub)
+
+    def solve(self, params: QPParams | None = None, **kw):
+        p = params if params is not None else qp_params_default(**kw)
+        qp_batch_solve(self.h, p)
+        return qp_batch_statuses(self.h, len(self.qps))
+
+    def result(self, i) -> Result:
+        q = self.qps[i]
+        st, x, y, info = qp_batch_result(self.h, i, q.n, q.m)
+        return Result(st, x, y, info)
+
+    def close(self):
+        qp_batch_destroy(self.h)
 
     def __enter__(self):
         return self

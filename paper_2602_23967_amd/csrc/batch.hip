@@ -1,0 +1,383 @@
+// batch.hip -- many independent QPs with a diagonal (or zero) Q solved in one
+// persistent launch.
+//
+// The instances are packed block-diagonally (variables and rows of instance b
+// are the ranges [voff[b], voff[b+1]) and [roff[b], roff[b+1])).  Each
+// workgroup takes the next instance from a work counter and runs the whole
+// method on it: the closed-form primal step (Section 2.2, diagonal Hessian),
+// the dual step (eqs. extrapolation, dual_update), the reflected Halpern
+// average (Section 3.1), the KKT test (Section 4), the certificates
+// (Section 5), the restart rule and the PID weight (Section 3.2) -- with its
+// own step sizes, restart state and status.  All reductions are workgroup
+// reductions broadcast to every thread, so every thread takes the same
+// decisions; nothing waits on another workgroup, and the only device-scope
+// atomic is the work counter, taken once per instance.
+#include <math.h>
+
+#include "device_math.h"
+#include "pdhcg_internal.h"
+
+namespace pdhcg {
+
+// a value every lane holds identically, moved to scalar registers
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum (bit j of MAXMASK clear) or max (bit set) of NR values over the
+// workgroup, in a fixed order; the result lands in every thread.
+template <int NR, unsigned MAXMASK>
+__device__ void wg_reduce(double (&v)[NR], double* lds)
+{
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kind = ((MAXMASK >> j) & 1u) ? R_MAX : R_SUM;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] = rcomb(kind, v[j], __shfl_xor(v[j], off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) lds[wave * NR + j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kind = ((MAXMASK >> j) & 1u) ? R_MAX : R_SUM;
+        double r = lds[j];
+#pragma unroll
+        for (int w = 1; w < TPB / 64; ++w) r = rcomb(kind, r, lds[w * NR + j]);
+        v[j] = uniform(r);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double row_dot(const int* rp, const int* col, const double* val,
+                                          const double* x, int row)
+{
+    double s = 0.0;
+    for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * x[col[q]];
+    return s;
+}
+
+// ---- ||A_b||_2 by power iteration on A_b'A_b, one instance per workgroup ----
+__global__ __launch_bounds__(TPB) void k_batch_norm(BatchDev B, double tol, long long max_iter,
+                                                   double* v, double* w, double* u, double* out)
+{
+    __shared__ double lds[2 * (TPB / 64)];
+    __shared__ int s_b;
+    for (;;) {
+        if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
+        __syncthreads();
+        const int b = s_b;
+        __syncthreads();
+        if (b >= B.count) return;
+        const int v0 = B.voff[b], n = B.voff[b + 1] - v0;
+        const int r0 = B.roff[b], m = B.roff[b + 1] - r0;
+        const int nnz = B.arp[r0 + m] - B.arp[r0];
+        if (m == 0 || nnz == 0) {
+            if (threadIdx.x == 0) out[b] = 0.0;
+            continue;
+        }
+        // start vector: SplitMix64 of the local index (seed 0), in [-1, 1)
+        double acc[1] = {0.0};
+        for (int j = threadIdx.x; j < n; j += TPB) {
+            unsigned long long z = (static_cast<unsigned long long>(j) + 1ull) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            const double val = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+            v[v0 + j] = val;
+            acc[0] += val * val;
+        }
+        wg_reduce<1, 0u>(acc, lds);
+        const double nv = sqrt(acc[0]);
+        for (int j = threadIdx.x; j < n; j += TPB) v[v0 + j] /= nv;
+        __syncthreads();
+        double sig = 0.0, prev = 0.0;
+        for (long long it = 1; it <= max_iter; ++it) {
+            acc[0] = 0.0;
+            for (int i = threadIdx.x; i < m; i += TPB) {
+                const double s = row_dot(B.arp, B.acol, B.aval, v, r0 + i);
+                w[r0 + i] = s;
+                acc[0] += s * s;
+            }
+            wg_reduce<1, 0u>(acc, lds);
+            sig = sqrt(acc[0]);
+            if (sig == 0.0) break;
+            acc[0] = 0.0;
+            for (int i = threadIdx.x; i < n; i += TPB) {
+                const double s = row_dot(B.trp, B.tcol, B.tval, w, v0 + i);
+                u[v0 + i] = s;
+                acc[0] += s * s;
+            }
+            wg_reduce<1, 0u>(acc, lds);
+            const double nu = sqrt(acc[0]);
+            if (nu == 0.0) break;
+            for (int i = threadIdx.x; i < n; i += TPB) v[v0 + i] = u[v0 + i] / nu;
+            __syncthreads();
+            if (fabs(sig - prev) <= tol * sig) break;
+            prev = sig;
+        }
+        if (threadIdx.x == 0) out[b] = sig;
+        __syncthreads();
+    }
+}
+
+// ---- the solve -----------------------------------------------------------------
+
+__device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds)
+{
+    const int v0 = B.voff[b], n = B.voff[b + 1] - v0;
+    const int r0 = B.roff[b], m = B.roff[b + 1] - r0;
+    const int tid = threadIdx.x;
+    double* x = B.x + v0;   double* xa = B.xa + v0; double* xt = B.xt + v0;
+    double* xbar = B.xbar;  double* aty = B.aty + v0; double* d = B.d + v0;
+    const double* c = B.c + v0; const double* qd = B.qd + v0;
+    const double* lv = B.lv + v0; const double* uv = B.uv + v0;
+    double* y = B.y + r0;   double* ya = B.ya + r0;  double* yt = B.yt;
+    double* ytil = B.ytil;
+    const double* lc = B.lc + r0; const double* uc = B.uc + r0;
+
+    const double eta = B.eta[b], omega0 = B.omega0[b];
+    double omega = omega0, tau = eta / omega, sigma = eta * omega, it = 1.0 / tau;
+    const int unb = B.unb[b];
+
+    for (int i = tid; i < n; i += TPB) {
+        const double v = clampd(0.0, lv[i], uv[i]);
+        x[i] = v; xa[i] = v; xt[i] = v;
+    }
+    for (int j = tid; j < m; j += TPB) {
+        y[j] = 0.0; ya[j] = 0.0; yt[r0 + j] = 0.0;
+    }
+    __syncthreads();
+
+    long long k = 0, t = 0, restarts = 0;
+    double R_start = 0.0, R_prev = 0.0, pid_int = 0.0, pid_prev = 0.0;
+    int R_prev_valid = 0, status = 0;
+    double ndx2 = 0.0, ndy2 = 0.0, ytil_max = 0.0, ptil_sum = 0.0, ptil_abs = 0.0, d_max = 0.0, cd = 0.0;
+    double rp_ = 0.0, rd_ = 0.0, rg_ = 0.0, pobj = 0.0, dobj = 0.0;
+
+    for (;;) {
+        if ((k > 0 || P.max_iter == 0) && (k % P.check_every == 0 || k >= P.max_iter)) {
+            // ---- check at (x_T, y_T): KKT pieces and certificate pieces ----------
+            double a[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) a[j] = 0.0;
+            // max slots: 0 1 4 7 8 9 13 15, the rest sums
+            constexpr unsigned kinds = (1u << 0) | (1u << 1) | (1u << 4) | (1u << 7) | (1u << 8) |
+                                       (1u << 9) | (1u << 13) | (1u << 15);
+            for (int i = tid; i < n; i += TPB) {
+                const double s = row_dot(B.trp, B.tcol, B.tval, yt, v0 + i);
+                aty[i] = s;
+                a[0] = rcomb(R_MAX, a[0], fabs(s));
+                if (k > 0) {
+                    const double wv = row_dot(B.trp, B.tcol, B.tval, ytil, v0 + i);
+                    const double wh = projR(wv, lv[i], uv[i]);
+                    a[1] = rcomb(R_MAX, a[1], fabs(wv - wh));
+                    a[2] += supp(-wh, lv[i], uv[i]);
+                    a[3] += supp_abs(-wh, lv[i], uv[i]);
+                }
+            }
+            for (int j = tid; j < m; j += TPB) {
+                const double s = row_dot(B.arp, B.acol, B.aval, B.xt, r0 + j);
+                a[4] = rcomb(R_MAX, a[4], fabs(s - clampd(s, lc[j], uc[j])));
+                const double yj = yt[r0 + j];
+                a[5] += supp(yj, lc[j], uc[j]);
+                const double dv = yj - ya[j];
+                a[6] += dv * dv;
+                if (k > 0 && unb) {
+                    const double ad = row_dot(B.arp, B.acol, B.aval, B.d, r0 + j);
+                    a[7] = rcomb(R_MAX, a[7], fabs(ad - projRec(ad, lc[j], uc[j])));
+                }
+            }
+            __syncthreads();
+            for (int i = tid; i < n; i += TPB) {
+                const double xi = xt[i], l = lv[i], u = uv[i];
+                const double qx = qd[i] * xi;
+                const double r = qx + c[i] + aty[i];
+                const double rh = projR(r, l, u);
+                a[8] = rcomb(R_MAX, a[8], fabs(r - rh));
+                a[9] = rcomb(R_MAX, a[9], fabs(qx));
+                a[10] += xi * qx;
+                a[11] += c[i] * xi;
+                a[12] += supp(-rh, l, u);
+                a[13] = rcomb(R_MAX, a[13], fabs(xi - clampd(xi - r, l, u)));
+                const double dv = xi - xa[i];
+                a[14] += dv * dv;
+                if (k > 0 && unb) a[15] = rcomb(R_MAX, a[15], fabs(qd[i] * d[i]));
+            }
+            wg_reduce<16, kinds>(a, lds);
+            const double cmax = B.cmax[b];
+            rp_ = a[4] / B.bscale[b];
+            double sd = a[9] > a[0] ? a[9] : a[0];
+            sd = sd > cmax ? sd : cmax;
+            rd_ = a[8] / (1.0 + sd);
+            pobj = 0.5 * a[10] + a[11];
+            const double dneg = 0.5 * a[10] + a[12] + a[5];
+            dobj = -dneg;
+            const double den = fabs(pobj) > fabs(dneg) ? fabs(pobj) : fabs(dneg);
+            rg_ = fabs(a[10] + a[11] + a[12] + a[5]) / (1.0 + den);
+            double worst = rp_ > rd_ ? rp_ : rd_;
+            worst = worst > rg_ ? worst : rg_;
+            bool pinf = false, dinf = false;
+            if (k > 0 && ytil_max > 0.0 && isfinite(ytil_max)) {
+                const double val = a[2] + ptil_sum;
+                const double imp = val < 0.0 ? -val : 0.0;
+                pinf = imp > 1e-9 * (a[3] + ptil_abs) && a[1] <= P.eps_inf * imp;
+            }
+            if (k > 0 && unb && d_max > 0.0 && isfinite(d_max) && cd / d_max < -P.tol) {
+                const double v1 = a[7] / d_max, v2 = a[15] / d_max / B.gammaq[b];
+                dinf = (v1 > v2 ? v1 : v2) <= P.eps_inf;
+            }
+            int restart = 0;
+            if (!isfinite(worst) || worst != worst) status = 5;
+            else if (worst <= P.tol) status = 1;
+            else if (pinf) status = 2;
+            else if (dinf) status = 3;
+            else if (k >= P.max_iter) status = 4;
+            else {
+                const double R = sqrt(omega * ndx2 + ndy2 / omega);
+                restart = R <= P.rs_suff * R_start ||
+                          (R_prev_valid && R <= P.rs_nec * R_start && R > R_prev) ||
+                          (double)t >= P.rs_art * (double)k;
+                R_prev = R;
+                R_prev_valid = 1;
+                if (restart) {
+                    const double mx = sqrt(a[14]), my = sqrt(a[6]);
+                    if (mx > 1e-10 && my > 1e-10 && isfinite(mx) && isfinite(my)) {
+                        const double so = sqrt(omega);
+                        const double e = log(so * mx / (my / so));
+                        pid_int += e;
+                        double lw = log(omega) - (P.kp * e + P.ki * pid_int + P.kd * (e - pid_prev));
+                        const double lo = log(omega0) - 10.0, hi = log(omega0) + 10.0;
+                        lw = lw < lo ? lo : (lw > hi ? hi : lw);
+                        omega = exp(lw);
+                        pid_prev = e;
+                    }
+                    tau = eta / omega;
+                    sigma = eta * omega;
+                    it = 1.0 / tau;
+                    t = 0;
+                    R_prev_valid = 0;
+                    ++restarts;
+                }
+            }
+            if (status) break;
+            if (restart) {
+                for (int i = tid; i < n; i += TPB) { x[i] = xt[i]; xa[i] = xt[i]; }
+                for (int j = tid; j < m; j += TPB) { y[j] = yt[r0 + j]; ya[j] = yt[r0 + j]; }
+                __syncthreads();
+            }
+        }
+        if (k >= P.max_iter) { status = 4; break; }
+        const bool store = ((k + 1) % P.check_every == 0) || (k + 1 >= P.max_iter);
+
+        // ---- primal step: closed form (Section 2.2) and x_bar ---------------------
+        for (int i = tid; i < n; i += TPB) {
+            const double s = row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
+            const double xi = x[i];
+            const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
+            xt[i] = v;
+            xbar[v0 + i] = 2.0 * v - xi;
+        }
+        __syncthreads();
+        // ---- dual step and Halpern on y --------------------------------------------
+        const double w = (double)(t + 1) / (double)(t + 2), wa = 1.0 / (double)(t + 2);
+        const double th = P.theta;
+        double a[7] = {0, 0, 0, 0, 0, 0, 0};
+        constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
+        for (int j = tid; j < m; j += TPB) {
+            const double s = row_dot(B.arp, B.acol, B.aval, xbar, r0 + j);
+            const double yj = y[j], l = lc[j], u = uc[j];
+            const double v = yj / sigma + s;
+            const double ytj = sigma * (v - clampd(v, l, u));
+            const double dy = ytj - yj;
+            a[1] += dy * dy;
+            yt[r0 + j] = ytj;
+            y[j] = P.use_halpern ? w * ((1.0 + th) * ytj - th * yj) + wa * ya[j] : ytj;
+            if (store) {
+                const double yy = projY(dy, l, u);
+                ytil[r0 + j] = yy;
+                a[2] = rcomb(R_MAX, a[2], fabs(yy));
+                a[3] += supp(yy, l, u);
+                a[4] += supp_abs(yy, l, u);
+            }
+        }
+        // ---- Halpern on x ---------------------------------------------------------
+        for (int i = tid; i < n; i += TPB) {
+            const double xti = xt[i], xi = x[i];
+            const double dx = xti - xi;
+            a[0] += dx * dx;
+            x[i] = P.use_halpern ? w * ((1.0 + th) * xti - th * xi) + wa * xa[i] : xti;
+            if (store && unb) {
+                const double di = projRec(dx, lv[i], uv[i]);
+                d[i] = di;
+                a[5] = rcomb(R_MAX, a[5], fabs(di));
+                a[6] += c[i] * di;
+            }
+        }
+        wg_reduce<7, kinds7>(a, lds);
+        ndx2 = a[0];
+        ndy2 = a[1];
+        if (store) {
+            ytil_max = a[2]; ptil_sum = a[3]; ptil_abs = a[4];
+            d_max = unb ? a[5] : 0.0;
+            cd = unb ? a[6] : 0.0;
+        }
+        ++k;
+        ++t;
+        if (t == 1) R_start = sqrt(omega * ndx2 + ndy2 / omega);
+    }
+    if (tid == 0) {
+        BatchOut o;
+        o.status = status;
+        o.pad = 0;
+        o.iterations = k;
+        o.restarts = restarts;
+        o.r_primal = rp_; o.r_dual = rd_; o.r_gap = rg_;
+        o.pobj = pobj; o.dobj = dobj; o.omega = omega;
+        o.ytil_max = ytil_max; o.d_max = d_max;
+        B.out[b] = o;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
+{
+    __shared__ double lds[16 * (TPB / 64)];
+    __shared__ int s_b;
+    for (;;) {
+        if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
+        __syncthreads();
+        const int b = s_b;
+        __syncthreads();
+        if (b >= B.count) return;
+        batch_solve_one(B, P, b, lds);
+    }
+}
+
+int batch_grid(int count)
+{
+    const int g = count < BATCH_GRID_MAX ? count : BATCH_GRID_MAX;
+    return g < 1 ? 1 : g;
+}
+
+hipError_t launch_batch_norm(const BatchDev& B, double tol, long long max_iter, double* v,
+                             double* w, double* u, double* out, hipStream_t s)
+{
+    k_batch_norm<<<batch_grid(B.count), TPB, 0, s>>>(B, tol, max_iter, v, w, u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s)
+{
+    k_batch_solve<<<batch_grid(B.count), TPB, 0, s>>>(B, P);
+    return hipGetLastError();
+}
+
+}  // namespace pdhcg

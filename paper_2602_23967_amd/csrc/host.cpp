@@ -960,6 +960,281 @@ int qp_kkt(qp_handle* h, const double* x, const double* y, double* out)
     return 0;
 }
 
+// ===========================================================================
+// batched solve
+// ===========================================================================
+
+}  // extern "C"
+
+struct qp_batch {
+    int64_t count = 0, n = 0, m = 0;
+    std::vector<int64_t> voff, roff;
+    BatchDev B;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    std::vector<BatchOut> out;
+    double eta_unused = 0.0;
+    std::vector<double> norm_A;
+    int solved = 0;
+    double setup_seconds = 0.0, solve_seconds = 0.0;
+};
+
+namespace {
+
+template <class T>
+int balloc(qp_batch* bt, T** p, size_t count)
+{
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+    bt->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return 0;
+}
+
+template <class T>
+int bupload(qp_batch* bt, const T** p, const T* src, size_t count)
+{
+    T* q = nullptr;
+    int rc = balloc(bt, &q, count);
+    if (rc) return rc;
+    if (count) HIPCHK(hipMemcpy(q, src, count * sizeof(T), hipMemcpyHostToDevice));
+    *p = q;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qp_batch_destroy(qp_batch* bt)
+{
+    if (!bt) return;
+    if (bt->stream) (void)hipStreamSynchronize(bt->stream);
+    for (void* p : bt->allocs) (void)hipFree(p);
+    if (bt->stream) (void)hipStreamDestroy(bt->stream);
+    delete bt;
+}
+
+int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_off,
+                    const int64_t* Qp, const int32_t* Qj, const double* Qv,
+                    const int64_t* Ap, const int32_t* Aj, const double* Av,
+                    const double* c, const double* b, const char* sense,
+                    const double* lb, const double* ub, qp_batch** out)
+{
+    const double t0 = now_s();
+    if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count >= INT32_MAX || !var_off || !row_off)
+        return fail(QP_ERR_INVALID_ARG, "need count >= 1 and instance offsets");
+    if (var_off[0] != 0 || row_off[0] != 0) return fail(QP_ERR_INVALID_ARG, "offsets must start at 0");
+    for (int64_t i = 0; i < count; ++i) {
+        if (var_off[i + 1] <= var_off[i]) return fail(QP_ERR_INVALID_ARG, "every instance needs >= 1 variable");
+        if (row_off[i + 1] < row_off[i]) return fail(QP_ERR_INVALID_ARG, "row offsets decrease");
+    }
+    const int64_t n = var_off[count], m = row_off[count];
+    if (n >= INT32_MAX || m >= INT32_MAX) return fail(QP_ERR_INVALID_ARG, "n and m must be below 2^31");
+    int rc;
+    std::vector<double> lvv(n), uvv(n), lcv(m), ucv(m);
+    for (int64_t i = 0; i < n; ++i) {
+        lvv[i] = lb ? lb[i] : -INFINITY;
+        uvv[i] = ub ? ub[i] : INFINITY;
+    }
+    if ((rc = check_bounds("lb/ub", n, lvv.data(), uvv.data()))) return rc;
+    if ((rc = check_vec("c", n, c, false))) return rc;
+    if (m > 0) {
+        if (!b || !sense) return fail(QP_ERR_INVALID_ARG, "b or sense is NULL");
+        if ((rc = check_vec("b", m, b, false))) return rc;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        switch (sense[i]) {
+        case 'E': lcv[i] = b[i]; ucv[i] = b[i]; break;
+        case 'G': lcv[i] = b[i]; ucv[i] = INFINITY; break;
+        case 'L': lcv[i] = -INFINITY; ucv[i] = b[i]; break;
+        default: return fail(QP_ERR_INVALID_ARG, "sense: unknown character at row " + std::to_string(i));
+        }
+    }
+    std::vector<int64_t> a_empty(1, 0);
+    if (!Ap) {
+        if (m != 0) return fail(QP_ERR_INVALID_ARG, "A: row pointer is NULL");
+        Ap = a_empty.data();
+    }
+    if ((rc = check_csr("A", m, n, Ap, Aj, Av))) return rc;
+    std::vector<double> qd(n, 0.0);
+    if (Qp) {
+        if ((rc = check_csr("Q", n, n, Qp, Qj, Qv))) return rc;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) {
+                if (Qj[k] != i) return fail(QP_ERR_INVALID_ARG, "batched solve needs a diagonal Q");
+                qd[i] += Qv[k];
+            }
+    }
+    for (int64_t i = 0; i < count; ++i)
+        for (int64_t r = row_off[i]; r < row_off[i + 1]; ++r)
+            for (int64_t k = Ap[r]; k < Ap[r + 1]; ++k)
+                if (Aj[k] < var_off[i] || Aj[k] >= var_off[i + 1])
+                    return fail(QP_ERR_INVALID_ARG, "A is not block-diagonal at row " + std::to_string(r));
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QP_ERR_DEVICE, "no HIP device available");
+    qp_batch* bt = new qp_batch();
+    auto bail = [&](int code) { qp_batch_destroy(bt); return code; };
+    bt->count = count;
+    bt->n = n;
+    bt->m = m;
+    bt->voff.assign(var_off, var_off + count + 1);
+    bt->roff.assign(row_off, row_off + count + 1);
+    if (hipStreamCreate(&bt->stream) != hipSuccess) return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    BatchDev& B = bt->B;
+    B.count = (int)count;
+    std::vector<int> vo32(count + 1), ro32(count + 1), arp32(m + 1);
+    for (int64_t i = 0; i <= count; ++i) { vo32[i] = (int)var_off[i]; ro32[i] = (int)row_off[i]; }
+    for (int64_t i = 0; i <= m; ++i) arp32[i] = (int)Ap[i];
+    std::vector<int64_t> tp;
+    std::vector<int32_t> tj;
+    std::vector<double> tv;
+    transpose(m, n, Ap, Aj, Av, tp, tj, tv);
+    std::vector<int> trp32(n + 1);
+    for (int64_t i = 0; i <= n; ++i) trp32[i] = (int)tp[i];
+    const int64_t nnz = Ap[m];
+    if ((rc = bupload(bt, &B.voff, vo32.data(), vo32.size())) || (rc = bupload(bt, &B.roff, ro32.data(), ro32.size())) ||
+        (rc = bupload(bt, &B.arp, arp32.data(), arp32.size())) || (rc = bupload(bt, &B.acol, Aj, (size_t)nnz)) ||
+        (rc = bupload(bt, &B.aval, Av, (size_t)nnz)) || (rc = bupload(bt, &B.trp, trp32.data(), trp32.size())) ||
+        (rc = bupload(bt, &B.tcol, tj.data(), tj.size())) || (rc = bupload(bt, &B.tval, tv.data(), tv.size())) ||
+        (rc = bupload(bt, &B.qd, qd.data(), (size_t)n)) || (rc = bupload(bt, &B.c, c, (size_t)n)) ||
+        (rc = bupload(bt, &B.lv, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv, uvv.data(), (size_t)n)) ||
+        (rc = bupload(bt, &B.lc, lcv.data(), (size_t)m)) || (rc = bupload(bt, &B.uc, ucv.data(), (size_t)m)))
+        return bail(rc);
+    double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d};
+    for (double** p : nv)
+        if ((rc = balloc(bt, p, (size_t)n))) return bail(rc);
+    double** mv[] = {&B.y, &B.ya, &B.yt, &B.ytil};
+    for (double** p : mv)
+        if ((rc = balloc(bt, p, (size_t)m))) return bail(rc);
+    if ((rc = balloc(bt, &B.queue, 1)) || (rc = balloc(bt, &B.out, (size_t)count))) return bail(rc);
+
+    // per-instance scalars: ||A_i||_2 on the device, the rest here
+    double* dnorm = nullptr;
+    if ((rc = balloc(bt, &dnorm, (size_t)count))) return bail(rc);
+    const qp_params dp = qp_params_default();
+    if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipMemsetAsync failed"));
+    if (launch_batch_norm(B, dp.power_tol, dp.power_max_iter, B.x, B.y, B.xt, dnorm, bt->stream) != hipSuccess ||
+        hipStreamSynchronize(bt->stream) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
+    bt->norm_A.resize(count);
+    if (hipMemcpy(bt->norm_A.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipMemcpy failed"));
+    std::vector<double> eta(count), om0(count), cmax(count), bsc(count), gq(count);
+    std::vector<int> unb(count, 0);
+    for (int64_t i = 0; i < count; ++i) {
+        const double na = bt->norm_A[i];
+        eta[i] = na * dp.norm_safety > 1e-12 ? dp.eta_scale / (dp.norm_safety * na) : 1.0;
+        double nb = 0.0, nc = 0.0, cm = 0.0, bl = 0.0, g = 1.0;
+        for (int64_t r = row_off[i]; r < row_off[i + 1]; ++r) {
+            const double bt_ = std::isfinite(lcv[r]) ? lcv[r] : (std::isfinite(ucv[r]) ? ucv[r] : 0.0);
+            nb += bt_ * bt_;
+            if (std::isfinite(lcv[r])) bl = std::max(bl, std::fabs(lcv[r]));
+            if (std::isfinite(ucv[r])) bl = std::max(bl, std::fabs(ucv[r]));
+        }
+        for (int64_t v = var_off[i]; v < var_off[i + 1]; ++v) {
+            nc += c[v] * c[v];
+            cm = std::max(cm, std::fabs(c[v]));
+            g = std::max(g, std::fabs(qd[v]));
+            if (!std::isfinite(lvv[v]) || !std::isfinite(uvv[v])) unb[i] = 1;
+        }
+        nb = std::sqrt(nb);
+        nc = std::sqrt(nc);
+        om0[i] = (nc > 1e-10 && nb > 1e-10) ? nc / nb : 1.0;
+        cmax[i] = cm;
+        bsc[i] = 1.0 + bl;
+        gq[i] = g;
+    }
+    if ((rc = bupload(bt, &B.eta, eta.data(), (size_t)count)) || (rc = bupload(bt, &B.omega0, om0.data(), (size_t)count)) ||
+        (rc = bupload(bt, &B.cmax, cmax.data(), (size_t)count)) || (rc = bupload(bt, &B.bscale, bsc.data(), (size_t)count)) ||
+        (rc = bupload(bt, &B.gammaq, gq.data(), (size_t)count)) || (rc = bupload(bt, &B.unb, unb.data(), (size_t)count)))
+        return bail(rc);
+    bt->setup_seconds = now_s() - t0;
+    *out = bt;
+    g_err.clear();
+    return 0;
+}
+
+int qp_batch_solve(qp_batch* bt, const qp_params* params)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    const qp_params p = params ? *params : qp_params_default();
+    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1) return fail(QP_ERR_INVALID_ARG, "invalid parameters");
+    BatchParams P{};
+    P.tol = p.tol; P.eps_inf = p.eps_inf; P.theta = p.theta;
+    P.kp = p.kp; P.ki = p.ki; P.kd = p.kd;
+    P.rs_suff = p.restart_sufficient; P.rs_nec = p.restart_necessary; P.rs_art = p.restart_artificial;
+    P.max_iter = p.max_iter; P.check_every = p.check_every; P.use_halpern = p.use_halpern;
+    const double t0 = now_s();
+    HIPCHK(hipMemsetAsync(bt->B.queue, 0, sizeof(int), bt->stream));
+    HIPCHK(launch_batch_solve(bt->B, P, bt->stream));
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    bt->solve_seconds = now_s() - t0;
+    bt->out.resize(bt->count);
+    HIPCHK(hipMemcpy(bt->out.data(), bt->B.out, sizeof(BatchOut) * bt->count, hipMemcpyDeviceToHost));
+    bt->solved = 1;
+    int opt = 0;
+    for (const BatchOut& o : bt->out) opt += o.status == QP_OPTIMAL;
+    g_err.clear();
+    return opt;
+}
+
+int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info* info)
+{
+    if (!bt || i < 0 || i >= bt->count) return fail(QP_ERR_INVALID_ARG, "bad batch or index");
+    if (!bt->solved) return fail(QP_ERR_STATE, "no solve has run on this batch");
+    const BatchOut& o = bt->out[i];
+    const int64_t v0 = bt->voff[i], n = bt->voff[i + 1] - v0, r0 = bt->roff[i], m = bt->roff[i + 1] - r0;
+    if (x) {
+        if (o.status == QP_DUAL_INFEASIBLE) {
+            HIPCHK(hipMemcpy(x, bt->B.d + v0, sizeof(double) * n, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < n; ++k) x[k] /= o.d_max;
+        } else {
+            HIPCHK(hipMemcpy(x, bt->B.xt + v0, sizeof(double) * n, hipMemcpyDeviceToHost));
+        }
+    }
+    if (y && m > 0) {
+        if (o.status == QP_PRIMAL_INFEASIBLE) {
+            HIPCHK(hipMemcpy(y, bt->B.ytil + r0, sizeof(double) * m, hipMemcpyDeviceToHost));
+            for (int64_t k = 0; k < m; ++k) y[k] /= o.ytil_max;
+        } else {
+            HIPCHK(hipMemcpy(y, bt->B.yt + r0, sizeof(double) * m, hipMemcpyDeviceToHost));
+        }
+    }
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = o.status;
+        info->iterations = o.iterations;
+        info->restarts = o.restarts;
+        info->r_primal = o.r_primal;
+        info->r_dual = o.r_dual;
+        info->r_gap = o.r_gap;
+        info->primal_obj = o.pobj;
+        info->dual_obj = o.dobj;
+        info->omega = o.omega;
+        info->norm_A = bt->norm_A[i];
+        info->solve_seconds = bt->solve_seconds;
+        info->setup_seconds = bt->setup_seconds;
+    }
+    return o.status;
+}
+
+int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    if (!bt->solved) return fail(QP_ERR_STATE, "no solve has run on this batch");
+    if (status)
+        for (int64_t i = 0; i < bt->count; ++i) status[i] = bt->out[i].status;
+    if (seconds) *seconds = bt->solve_seconds;
+    return 0;
+}
+
 int64_t qp_spmv_schedule(int64_t rows, const int64_t* rowptr, int32_t* out, int64_t cap)
 {
     if (rows < 0 || !rowptr) return fail(QP_ERR_INVALID_ARG, "bad argument");

@@ -13,10 +13,12 @@ constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at mos
 constexpr int VEC_GRID_MAX = 2048;
 // XCD-aware column partitioning: an operand larger than PART_MIN_COLS
 // doubles is split into NPARTS contiguous column parts; block b of the
-// product works on part b % NPARTS, which on gfx950's round-robin dispatch
-// keeps each XCD's gathers inside one part (1/8 of the operand, L2-resident)
+// product works on part b % NPARTS, which on gfx950's round-robin dispatch of
+// blocks to its 8 XCDs keeps each XCD's gathers inside one part (1/4 of the
+// operand, L2-resident).  4 parts measured faster than 8 (half the partial
+// row traffic, gathers still L2 hits).
 #ifndef PDHCG_NPARTS
-#define PDHCG_NPARTS 8
+#define PDHCG_NPARTS 4
 #endif
 constexpr int NPARTS = PDHCG_NPARTS;
 constexpr int PART_MIN_COLS = 262144;
@@ -146,5 +148,44 @@ hipError_t launch_dot(const DevState& S, const double* a, const double* b, int l
                       hipStream_t s);
 
 int vec_grid(long long len);
+
+// ---- batched solve of many QPs with diagonal Q (batch.hip) ----------------------
+
+constexpr int BATCH_GRID_MAX = 2048;   // persistent workgroups (instances are queued)
+
+struct BatchOut {
+    int status, pad;
+    long long iterations, restarts;
+    double r_primal, r_dual, r_gap, pobj, dobj, omega, ytil_max, d_max;
+};
+
+struct BatchParams {
+    double tol, eps_inf, theta, kp, ki, kd, rs_suff, rs_nec, rs_art;
+    long long max_iter, check_every;
+    int use_halpern, pad;
+};
+
+struct BatchDev {
+    int count = 0;
+    int* queue = nullptr;                       // work counter (instances taken)
+    const int *voff = nullptr, *roff = nullptr; // count + 1 each
+    const int *arp = nullptr, *acol = nullptr;  // A, global indices
+    const double* aval = nullptr;
+    const int *trp = nullptr, *tcol = nullptr;  // A'
+    const double* tval = nullptr;
+    const double *qd = nullptr, *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
+    // per instance
+    const double *eta = nullptr, *omega0 = nullptr, *cmax = nullptr, *bscale = nullptr, *gammaq = nullptr;
+    const int* unb = nullptr;
+    // state (packed like the problem)
+    double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
+    double *xbar = nullptr, *aty = nullptr, *d = nullptr, *ytil = nullptr;
+    BatchOut* out = nullptr;
+};
+
+int batch_grid(int count);
+hipError_t launch_batch_norm(const BatchDev& B, double tol, long long max_iter, double* v,
+                             double* w, double* u, double* out, hipStream_t s);
+hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s);
 
 }  // namespace pdhcg

@@ -77,8 +77,6 @@ def _csr(M) -> sp.csr_matrix:
     M = sp.csr_matrix(M)
     M.sum_duplicates()
     M.sort_indices()
-    M.indptr = M.indptr.astype(np.int64)
-    M.indices = M.indices.astype(np.int32)
     return M
 
 
@@ -345,3 +343,77 @@ def box_infeasible_rows(instance: int = 0, n: int = 8, m: int = 3) -> QP:
     q.sense = bytes(s)
     q.name = f"box_infeasible{instance}"
     return q
+
+
+FAM_MPC = 3
+
+
+def mpc(instance: int = 0, horizon: int | None = None, infeasible: bool = False) -> QP:
+    """Linear MPC QP over a horizon T ~ U{10..50}: states x_0..x_T (12 each),
+    inputs u_0..u_{T-1} (4 each).  Rows: x_0 = x_init (12 '='), then
+    x_{t+1} - A_d x_t - B_d u_t = 0 (12 '=' rows per step, 17 nonzeros each).
+    A_d = U diag(lam) U' with U a random orthogonal matrix and lam ~ U(-0.95,
+    0.95) rescaled so max |lam| = 0.95; B_d ~ N(0, 0.3).  Q = I on states,
+    0.1 I on inputs, c = 0.  Bounds |u| <= 1, |x| <= 5; x_init ~ U(-1, 1).
+    Variables are ordered x_0, u_0, x_1, u_1, ..., x_T.
+    ``infeasible`` sets x_init[0] = 6, outside the state box."""
+    rng = rng_for(FAM_MPC, instance)
+    T = int(rng.integers(10, 51)) if horizon is None else int(horizon)
+    ns, nu = 12, 4
+    G = rng.normal(size=(ns, ns))
+    U, _ = np.linalg.qr(G)
+    lam = rng.uniform(-0.95, 0.95, size=ns)
+    lam *= 0.95 / np.abs(lam).max()
+    Ad = U @ np.diag(lam) @ U.T
+    Bd = rng.normal(0.0, 0.3, size=(ns, nu))
+    xinit = rng.uniform(-1.0, 1.0, size=ns)
+    if infeasible:
+        xinit[0] = 6.0
+    step = ns + nu
+    n = step * T + ns
+    xo = lambda t: t * step              # offset of x_t
+    uo = lambda t: t * step + ns         # offset of u_t
+    rows, cols, vals = [], [], []
+    for i in range(ns):                  # x_0 = x_init
+        rows.append(i); cols.append(xo(0) + i); vals.append(1.0)
+    r = ns
+    for t in range(T):
+        for i in range(ns):
+            rows += [r] * (1 + ns + nu)
+            cols += [xo(t + 1) + i] + [xo(t) + j for j in range(ns)] + [uo(t) + k for k in range(nu)]
+            vals += [1.0] + list(-Ad[i]) + list(-Bd[i])
+            r += 1
+    m = r
+    A = _csr(sp.csr_matrix((vals, (rows, cols)), shape=(m, n)))
+    qd = np.ones(n)
+    for t in range(T):
+        qd[uo(t):uo(t) + nu] = 0.1
+    lb = np.full(n, -5.0)
+    ub = np.full(n, 5.0)
+    for t in range(T):
+        lb[uo(t):uo(t) + nu] = -1.0
+        ub[uo(t):uo(t) + nu] = 1.0
+    b = np.zeros(m)
+    b[:ns] = xinit
+    return QP(n=n, m=m, Q=_csr(sp.diags(qd)), A=A, c=np.zeros(n), b=b, sense=b"E" * m,
+              lb=lb, ub=ub, name=f"mpc{instance}_T{T}" + ("_infeasible" if infeasible else ""),
+              meta={"T": T, "xinit": xinit})
+
+
+def pack(qps):
+    """Block-diagonal packing of several QPs (one problem whose variables and
+    rows are the instances' in order).  Returns (QP, var_off, row_off)."""
+    var_off = np.zeros(len(qps) + 1, dtype=np.int64)
+    row_off = np.zeros(len(qps) + 1, dtype=np.int64)
+    for i, q in enumerate(qps):
+        var_off[i + 1] = var_off[i] + q.n
+        row_off[i + 1] = row_off[i] + q.m
+    Qs = [q.Q.tocoo() if q.Q is not None else sp.coo_matrix((q.n, q.n)) for q in qps]
+    Q = _csr(sp.block_diag(Qs, format="coo"))
+    A = _csr(sp.block_diag([q.A.tocoo() for q in qps], format="coo"))
+    qp = QP(n=int(var_off[-1]), m=int(row_off[-1]), Q=Q, A=A,
+            c=np.concatenate([q.c for q in qps]), b=np.concatenate([q.b for q in qps]),
+            sense=b"".join(q.sense for q in qps),
+            lb=np.concatenate([q.lb for q in qps]), ub=np.concatenate([q.ub for q in qps]),
+            name=f"pack{len(qps)}")
+    return qp, var_off, row_off

@@ -155,3 +155,25 @@ def test_no_device_gives_device_error_or_success():
         assert e.code == P.ERR_DEVICE
     else:
         P.qp_destroy(h)
+
+
+def test_batch_validation_errors():
+    from paper_2602_23967_amd.instances import pack
+    qs = [I.mpc(i, horizon=10) for i in range(3)]
+    big, vo, ro = pack(qs)
+    mk = lambda **kw: (lambda: P.qp_batch_create(kw.get("count", 3), kw.get("vo", vo), kw.get("ro", ro),
+                                                 kw.get("Q", big.Q), kw.get("A", big.A), big.c, big.b,
+                                                 big.sense, big.lb, big.ub))
+    _bad(mk(count=0), P.ERR_INVALID_ARG)
+    vo2 = vo.copy(); vo2[1] = vo2[0]
+    _bad(mk(vo=vo2), P.ERR_INVALID_ARG)                       # empty instance
+    A2 = big.A.tolil(); A2[0, int(vo[1]) + 1] = 1.0           # entry outside its block
+    _bad(mk(A=A2.tocsr()), P.ERR_INVALID_ARG)
+    Qn = big.Q.tolil(); Qn[0, 1] = 0.5; Qn[1, 0] = 0.5        # non-diagonal Q
+    _bad(mk(Q=Qn.tocsr()), P.ERR_INVALID_ARG)
+    try:
+        h = mk()()
+    except P.QPError as e:
+        assert e.code == P.ERR_DEVICE                          # no GPU here
+    else:
+        P.qp_batch_destroy(h)

@@ -1,0 +1,120 @@
+"""Batched solve (many QPs with diagonal Q in one persistent launch) against
+the oracle, instance by instance, through the C ABI."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import paper_2602_23967_amd as P
+from paper_2602_23967_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need the MI355X"
+    return T
+
+
+def _unbounded_lp():
+    """LP with a free variable that no row touches and a negative cost: the
+    problem is unbounded along e_0 (diagonal Q = 0 fits the batch path)."""
+    q = I.tiny_lp(40)
+    A = q.A.toarray()
+    A[:, 0] = 0.0
+    q.A = sp.csr_matrix(A)
+    q.lb = q.lb.copy(); q.ub = q.ub.copy()
+    q.lb[0], q.ub[0] = -np.inf, np.inf
+    q.c = q.c.copy(); q.c[0] = -1.0
+    q.b = q.A @ np.full(q.n, 1.0)
+    q.name = "unbounded_lp"
+    return q
+
+
+@pytest.fixture(scope="module")
+def mix():
+    qs = [I.mpc(i) for i in range(20)]
+    qs += [I.mpc(100, infeasible=True), I.mpc(101, infeasible=True)]
+    qs += [I.portfolio(5, n_assets=3000, k_factors=20), I.tiny_lp(3), _unbounded_lp()]
+    return qs
+
+
+def test_batch_matches_oracle(torch, mix):
+    with P.BatchSolver(mix) as bs:
+        st, secs = bs.solve()
+        res = [bs.result(i) for i in range(len(mix))]
+    for q, g in zip(mix, res):
+        o = oracle.solve(q, max_iter=100000)
+        assert g.status == o.status, (q.name, g.status_name, o.status_name)
+        if o.status == oracle.OPTIMAL:
+            k = oracle.kkt(q, g.x, g.y)
+            assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6, (q.name, k)
+            ref = oracle.solve(q, tol=1e-9, max_iter=400000)
+            f, fr = g.info["primal_obj"], ref.info["primal_obj"]
+            assert abs(f - fr) <= 1e-6 * (1 + abs(fr)), (q.name, f, fr)
+            assert np.all(g.x >= q.lb) and np.all(g.x <= q.ub)
+        elif o.status == oracle.PRIMAL_INFEASIBLE:
+            assert np.abs(g.y).max() == pytest.approx(1.0)
+        elif o.status == oracle.DUAL_INFEASIBLE:
+            d = g.x
+            assert np.abs(d).max() == pytest.approx(1.0) and q.c @ d < 0
+            assert np.abs(q.A @ d).max() <= 1e-8
+    assert list(st) == [r.status for r in res]
+
+
+def test_batch_alone_equals_in_the_mix(torch, mix):
+    """An instance's result does not depend on the other instances of the
+    launch (bitwise)."""
+    with P.BatchSolver(mix) as bs:
+        bs.solve()
+        together = [bs.result(i) for i in (3, 7, 21)]
+    for i, g in zip((3, 7, 21), together):
+        with P.BatchSolver([mix[i]]) as one:
+            one.solve()
+            a = one.result(0)
+        assert a.status == g.status and a.info["iterations"] == g.info["iterations"]
+        assert np.array_equal(a.x, g.x) and np.array_equal(a.y, g.y)
+
+
+def test_batch_deterministic_and_limits(torch):
+    qs = [I.mpc(i) for i in range(30, 36)]
+    with P.BatchSolver(qs) as bs:
+        bs.solve()
+        r1 = [bs.result(i) for i in range(len(qs))]
+        bs.solve()
+        r2 = [bs.result(i) for i in range(len(qs))]
+        st0, _ = bs.solve(max_iter=0)
+        assert np.all(st0 == P.ITERATION_LIMIT)
+        st1, _ = bs.solve(max_iter=10)
+        assert np.all(st1 == P.ITERATION_LIMIT)
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+
+
+def test_batch_agrees_with_single_path(torch):
+    """The one-instance path (separate kernels per step) and the batched
+    path reach the same optimum."""
+    q = I.mpc(7)
+    with P.BatchSolver([q]) as bs:
+        bs.solve()
+        gb = bs.result(0)
+    with P.Solver(q) as s:
+        gs = s.solve()
+    assert gb.status == gs.status == P.OPTIMAL
+    assert gb.info["primal_obj"] == pytest.approx(gs.info["primal_obj"], rel=1e-6, abs=1e-9)
+    assert np.abs(gb.x - gs.x).max() <= 1e-4
+
+
+def test_batch_many_instances(torch):
+    qs = [I.mpc(i) for i in range(200, 712)]
+    with P.BatchSolver(qs) as bs:
+        st, secs = bs.solve()
+        print(f"512 MPC instances: {secs * 1e3:.1f} ms, {np.sum(st == P.OPTIMAL)} optimal")
+        assert np.all(st == P.OPTIMAL)
+        for i in (0, 255, 511):
+            g = bs.result(i)
+            k = oracle.kkt(qs[i], g.x, g.y)
+            assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6
