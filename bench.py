@@ -82,6 +82,80 @@ def cpu_baseline(q, gpu_units_per_solve, sample_iters):
     }
 
 
+def batch_bytes(q, iters):
+    """Algorithmic bytes of one instance's iterations in the batched kernel:
+    the A and A' products (12 B per nonzero each, int32 row pointers),
+    the primal step (x, c, q, l_v, u_v read; x_T, x_bar written), the dual
+    step (x_bar gathered once; y, y anchor, l_c, u_c read; y_T, y written)
+    and the Halpern step on x (x_T, x, anchor read; x written)."""
+    per_iter = 24 * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * (7 + 1 + 4) + 8 * q.m * 6
+    return per_iter * iters
+
+
+def main_batch(args, torch, P, I):
+    t = time.perf_counter()
+    qs = [I.mpc(i) for i in range(args.count)]
+    log(f"generated {len(qs)} MPC instances in {time.perf_counter() - t:.1f}s "
+        f"(n {sum(q.n for q in qs)}, m {sum(q.m for q in qs)}, nnz(A) {sum(q.nnz_A for q in qs)})")
+    bs = P.BatchSolver(qs)
+    params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
+    for w in range(args.warmup):
+        st, sec = bs.solve(params)
+        log(f"warmup {w}: {int(np.sum(st == P.OPTIMAL))}/{len(qs)} optimal in {sec * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    lat = []
+    t_start = time.perf_counter()
+    for s_ in range(args.steps):
+        a = time.perf_counter()
+        st, sec = bs.solve(params)
+        lat.append(time.perf_counter() - a)
+        log(f"step {s_}: {int(np.sum(st == P.OPTIMAL))}/{len(qs)} optimal in {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    infos = [bs.result(i).info for i in range(len(qs))]
+    iters = [i["iterations"] for i in infos]
+    nbytes = sum(batch_bytes(q, it) for q, it in zip(qs, iters))
+    kernel_s = float(np.median(lat))
+    bs.close()
+    # the same instances one at a time through the single-QP path, FP64
+    one = []
+    for q in qs[: args.one_at_a_time]:
+        with P.Solver(q) as s1:
+            r = s1.solve(params)
+            one.append(r.info["solve_seconds"])
+    out = {
+        "metric": METRIC,
+        "value": len(qs) * args.steps / elapsed,
+        "unit": "QPs solved/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched linear MPC, {len(qs)} instances, horizon T ~ U{{10..50}}, "
+                               f"12 states, 4 inputs, one persistent launch, tol {args.tol:g}",
+                   "instances": len(qs)},
+        "solved": bool(np.all(st == P.OPTIMAL)),
+        "iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
+        "roofline": {"bound": "hbm", "achieved": nbytes / kernel_s / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_solve", "bytes_per_launch": nbytes, "avg_us": kernel_s * 1e6},
+        "one_at_a_time": {"value": 1.0 / float(np.mean(one)), "unit": "QPs solved/s",
+                          "sample": f"first {len(one)} instances, qp_solve each (FP64, same GPU)"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        ns = 0
+        while ns < len(qs) and time.perf_counter() - t < 10.0:
+            oracle.solve(qs[ns], tol=args.tol)
+            ns += 1
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": ns / el, "unit": "QPs solved/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle_qp_solve on the first {ns} instances, one at a time ({el:.1f}s)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +167,10 @@ def main():
     ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
     ap.add_argument("--max-iter", type=int, default=100000,
                     help="outer iteration cap (lower only for short profiling runs)")
+    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch"], default="large_sparse")
+    ap.add_argument("--count", type=int, default=4096, help="instances of the batched workload")
+    ap.add_argument("--one-at-a-time", type=int, default=32,
+                    help="instances of the batched workload also solved one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 64 MiB (scale for rocprofv3 byte counters)")
@@ -120,6 +198,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "mpc_batch":
+        return main_batch(args, torch, P, I)
 
     t = time.perf_counter()
     q = I.large_sparse(0, n=args.n)
@@ -158,7 +238,11 @@ def main():
     ms = sum(i["fam_ms"][f] for i in infos)
     avg_us = 1e3 * ms / max(timed, 1)
     nbytes = hp_bytes(q.n, q.nnz_Q)
-    achieved = nbytes / (avg_us * 1e-6) / 1e9 if timed else None
+    # launches that found the inner solve already stopped return at once; their
+    # time stays in the denominator, their bytes do not count
+    launches = sum(i["fam_launches"][f] for i in infos)
+    active = sum(i["spmv_hp_active"] for i in infos)
+    achieved = nbytes * active / (avg_us * 1e-6 * launches) / 1e9 if timed else None
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
@@ -195,8 +279,9 @@ def main():
                        "inner_per_s": infos[-1]["inner_iterations"] / np.median(lat)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                     "kernel": "k_spmv<EpiStepA> (inner H p)", "bytes_per_launch": nbytes,
-                     "avg_us": avg_us, "timed_launches": timed},
+                     "kernel": "inner H p product (k_spmv<EpiStepA> + k_rows<EpiStepA>)",
+                     "bytes_per_launch": nbytes, "avg_us": avg_us, "timed_launches": timed,
+                     "launches": launches, "active_launches": active},
         "kernels": kern,
         "setup_s": info["setup_seconds"],
     }

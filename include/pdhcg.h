@@ -116,6 +116,8 @@ typedef struct {
     double fam_ms[QP_NFAM];    /* summed device time of the timed launches */
     int64_t fam_timed[QP_NFAM];/* number of timed launches */
     int64_t fam_launches[QP_NFAM]; /* number of launches */
+    int64_t spmv_hp_active;    /* QP_FAM_SPMV_HP launches that ran (the rest found the
+                                  inner solve already stopped and returned at once) */
 } qp_info;
 
 /* Defaults listed above. */
@@ -203,17 +205,17 @@ int qp_norms(const qp_handle* h, double* norm_A, double* norm_Q);
 
 /* ---- batched solve: many independent QPs in one persistent launch --------
  *
- * For many small QPs with a diagonal (or zero) Q -- the case where the
- * primal step is the closed form of Section 2.2, e.g. linear MPC -- solved
- * together.  The caller packs the instances block-diagonally: instance i
- * owns variables [var_off[i], var_off[i+1]) and rows [row_off[i],
- * row_off[i+1]); Q (n x n, diagonal entries only, or NULL) and A (m x n,
+ * For many small QPs (e.g. linear MPC, small factor models) solved together.
+ * The caller packs the instances block-diagonally: instance i owns variables
+ * [var_off[i], var_off[i+1]) and rows [row_off[i], row_off[i+1]); Q (n x n,
+ * symmetric, every entry inside its instance's block, or NULL) and A (m x n,
  * every entry inside its instance's block) are CSR as in qp_create, as are
  * c, b, sense, lb, ub over all instances.  Each instance runs the method of
- * qp_solve with its own step sizes, restarts, weight and status; one
- * workgroup solves one instance at a time, so an instance's result does not
- * depend on which other instances share the launch.  Same ownership and
- * error rules as qp_create. */
+ * qp_solve with its own step sizes, restarts, weight, inner tolerance and
+ * status: the closed-form primal step when its block of Q is diagonal, the
+ * boxed conjugate-gradient inner solve otherwise.  One workgroup solves one
+ * instance at a time, so an instance's result does not depend on which other
+ * instances share the launch.  Same ownership and error rules as qp_create. */
 typedef struct qp_batch qp_batch;
 
 int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_off,

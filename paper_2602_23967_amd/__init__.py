@@ -56,7 +56,7 @@ class QPInfo(C.Structure):
                 ("norm_A", C.c_double), ("norm_Q", C.c_double), ("eps_inner", C.c_double),
                 ("solve_seconds", C.c_double), ("setup_seconds", C.c_double),
                 ("fam_ms", C.c_double * NFAM), ("fam_timed", _i64 * NFAM),
-                ("fam_launches", _i64 * NFAM)]
+                ("fam_launches", _i64 * NFAM), ("spmv_hp_active", _i64)]
 
     def as_dict(self):
         d = {}

@@ -56,6 +56,32 @@ __device__ void wg_reduce(double (&v)[NR], double* lds)
     __syncthreads();
 }
 
+// sums of slots 0 and 1, minimum of slot 2, over the workgroup (in every thread)
+__device__ void wg_reduce_min3(double (&v)[3], double* lds)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int kind = j == 2 ? R_MIN : R_SUM;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] = rcomb(kind, v[j], __shfl_xor(v[j], off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) lds[wave * 3 + j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int kind = j == 2 ? R_MIN : R_SUM;
+        double r = lds[j];
+#pragma unroll
+        for (int w = 1; w < TPB / 64; ++w) r = rcomb(kind, r, lds[w * 3 + j]);
+        v[j] = uniform(r);
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ double row_dot(const int* rp, const int* col, const double* val,
                                           const double* x, int row)
 {
@@ -64,22 +90,27 @@ __device__ __forceinline__ double row_dot(const int* rp, const int* col, const d
     return s;
 }
 
-// ---- ||A_b||_2 by power iteration on A_b'A_b, one instance per workgroup ----
-__global__ __launch_bounds__(TPB) void k_batch_norm(BatchDev B, double tol, long long max_iter,
-                                                   double* v, double* w, double* u, double* out)
+// ---- ||M_b||_2 by power iteration on M_b'M_b, one instance per workgroup ----
+__global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const int* rowoff,
+                                                   const int* coloff, const int* mrp,
+                                                   const int* mcol, const double* mval,
+                                                   const int* trp, const int* tcol,
+                                                   const double* tval, const int* sel, double tol,
+                                                   long long max_iter, double* v, double* w,
+                                                   double* u, double* out)
 {
     __shared__ double lds[2 * (TPB / 64)];
     __shared__ int s_b;
     for (;;) {
-        if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
+        if (threadIdx.x == 0) s_b = atomicAdd(queue, 1);
         __syncthreads();
         const int b = s_b;
         __syncthreads();
-        if (b >= B.count) return;
-        const int v0 = B.voff[b], n = B.voff[b + 1] - v0;
-        const int r0 = B.roff[b], m = B.roff[b + 1] - r0;
-        const int nnz = B.arp[r0 + m] - B.arp[r0];
-        if (m == 0 || nnz == 0) {
+        if (b >= count) return;
+        const int c0 = coloff[b], n = coloff[b + 1] - c0;
+        const int r0 = rowoff[b], m = rowoff[b + 1] - r0;
+        const int nnz = mrp[r0 + m] - mrp[r0];
+        if (m == 0 || nnz == 0 || (sel && !sel[b])) {
             if (threadIdx.x == 0) out[b] = 0.0;
             continue;
         }
@@ -91,18 +122,18 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(BatchDev B, double tol, long
             z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
             z ^= z >> 31;
             const double val = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
-            v[v0 + j] = val;
+            v[c0 + j] = val;
             acc[0] += val * val;
         }
         wg_reduce<1, 0u>(acc, lds);
         const double nv = sqrt(acc[0]);
-        for (int j = threadIdx.x; j < n; j += TPB) v[v0 + j] /= nv;
+        for (int j = threadIdx.x; j < n; j += TPB) v[c0 + j] /= nv;
         __syncthreads();
         double sig = 0.0, prev = 0.0;
         for (long long it = 1; it <= max_iter; ++it) {
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < m; i += TPB) {
-                const double s = row_dot(B.arp, B.acol, B.aval, v, r0 + i);
+                const double s = row_dot(mrp, mcol, mval, v, r0 + i);
                 w[r0 + i] = s;
                 acc[0] += s * s;
             }
@@ -111,14 +142,14 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(BatchDev B, double tol, long
             if (sig == 0.0) break;
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < n; i += TPB) {
-                const double s = row_dot(B.trp, B.tcol, B.tval, w, v0 + i);
-                u[v0 + i] = s;
+                const double s = row_dot(trp, tcol, tval, w, c0 + i);
+                u[c0 + i] = s;
                 acc[0] += s * s;
             }
             wg_reduce<1, 0u>(acc, lds);
             const double nu = sqrt(acc[0]);
             if (nu == 0.0) break;
-            for (int i = threadIdx.x; i < n; i += TPB) v[v0 + i] = u[v0 + i] / nu;
+            for (int i = threadIdx.x; i < n; i += TPB) v[c0 + i] = u[c0 + i] / nu;
             __syncthreads();
             if (fabs(sig - prev) <= tol * sig) break;
             prev = sig;
@@ -143,9 +174,12 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     double* ytil = B.ytil;
     const double* lc = B.lc + r0; const double* uc = B.uc + r0;
 
-    const double eta = B.eta[b], omega0 = B.omega0[b];
+    double* rhs = B.rhs + v0; double* g = B.g + v0; double* p = B.p + v0; double* hp = B.hp + v0;
+    const double eta = B.eta[b], omega0 = B.omega0[b], normq = B.normq[b];
     double omega = omega0, tau = eta / omega, sigma = eta * omega, it = 1.0 / tau;
-    const int unb = B.unb[b];
+    const int unb = B.unb[b], qgen = B.qgen[b];
+    double eps = INFINITY;
+    long long inner_total = 0;
 
     for (int i = tid; i < n; i += TPB) {
         const double v = clampd(0.0, lv[i], uv[i]);
@@ -198,7 +232,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             __syncthreads();
             for (int i = tid; i < n; i += TPB) {
                 const double xi = xt[i], l = lv[i], u = uv[i];
-                const double qx = qd[i] * xi;
+                const double qx = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) : qd[i] * xi;
                 const double r = qx + c[i] + aty[i];
                 const double rh = projR(r, l, u);
                 a[8] = rcomb(R_MAX, a[8], fabs(r - rh));
@@ -209,7 +243,10 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 a[13] = rcomb(R_MAX, a[13], fabs(xi - clampd(xi - r, l, u)));
                 const double dv = xi - xa[i];
                 a[14] += dv * dv;
-                if (k > 0 && unb) a[15] = rcomb(R_MAX, a[15], fabs(qd[i] * d[i]));
+                if (k > 0 && unb) {
+                    const double qdv = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.d, v0 + i) : qd[i] * d[i];
+                    a[15] = rcomb(R_MAX, a[15], fabs(qdv));
+                }
             }
             wg_reduce<16, kinds>(a, lds);
             const double cmax = B.cmax[b];
@@ -277,15 +314,108 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         if (k >= P.max_iter) { status = 4; break; }
         const bool store = ((k + 1) % P.check_every == 0) || (k + 1 >= P.max_iter);
 
-        // ---- primal step: closed form (Section 2.2) and x_bar ---------------------
-        for (int i = tid; i < n; i += TPB) {
-            const double s = row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
-            const double xi = x[i];
-            const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
-            xt[i] = v;
-            xbar[v0 + i] = 2.0 * v - xi;
+        if (!qgen) {
+            // ---- primal step: closed form (Section 2.2) and x_bar -----------------
+            for (int i = tid; i < n; i += TPB) {
+                const double s = row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
+                const double xi = x[i];
+                const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
+                xt[i] = v;
+                xbar[v0 + i] = 2.0 * v - xi;
+            }
+            __syncthreads();
+        } else {
+            // ---- primal step: boxed CG (MPRGP) on 1/2 x'(Q + I/tau)x - rhs'x -----
+            const double abar = P.abar_scale / (normq + it);
+            double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
+            for (int i = tid; i < n; i += TPB) {
+                const double r = x[i] * it - c[i] - row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
+                rhs[i] = r;
+                const double xi = xt[i];
+                const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - r;
+                g[i] = gi;
+                const Split sp = split(xi, gi, lv[i], uv[i], abar);
+                st[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+                st[1] += sp.beta * sp.beta;
+                st[2] += sp.phit * sp.phi;
+            }
+            wg_reduce<3, 0u>(st, lds);
+            if (isinf(eps) && P.eps_fixed <= 0.0) eps = fmax(P.gamma_inner * sqrt(st[0]), P.eps_min);
+            const double eps_use = P.eps_fixed > 0.0 ? P.eps_fixed : eps;
+            long long inner = 0;
+            int last = STEP_NONE;
+            double gam = 0.0;
+            bool done = sqrt(st[0]) <= eps_use || P.max_inner <= 0;
+            int mode = (st[1] <= P.mprgp_gamma * P.mprgp_gamma * st[2]) ? DIR_PHI : DIR_BETA;
+            while (!done) {
+                for (int i = tid; i < n; i += TPB) {
+                    const Split sp = split(xt[i], g[i], lv[i], uv[i], abar);
+                    p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
+                }
+                __syncthreads();
+                double hs[3] = {0.0, 0.0, INFINITY};   // p'Hp, g'p, feasible step
+                for (int i = tid; i < n; i += TPB) {
+                    const double pi = p[i], xi = xt[i];
+                    const double h = row_dot(B.qrp, B.qcol, B.qval, B.p, v0 + i) + it * pi;
+                    hp[i] = h;
+                    hs[0] += pi * h;
+                    hs[1] += g[i] * pi;
+                    double fs = INFINITY;
+                    if (pi > 0.0 && isfinite(lv[i])) fs = (xi - lv[i]) / pi;
+                    else if (pi < 0.0 && isfinite(uv[i])) fs = (xi - uv[i]) / pi;
+                    hs[2] = fmin(hs[2], fs);
+                }
+                wg_reduce_min3(hs, lds);
+                if (!(hs[0] > 0.0)) break;
+                const double af = hs[2] < 0.0 ? 0.0 : hs[2];
+                const double acg = hs[1] / hs[0];
+                int kind;
+                double alpha;
+                if (mode == DIR_BETA) { kind = STEP_PROP; alpha = acg < af ? acg : af; }
+                else if (acg <= af) { kind = STEP_CG; alpha = acg; }
+                else { kind = STEP_EXPAND; alpha = af; }
+                double us[4] = {0.0, 0.0, 0.0, 0.0};   // stats and phi'Hp
+                for (int i = tid; i < n; i += TPB) {
+                    const double l = lv[i], u = uv[i];
+                    double xi = clampd(xt[i] - alpha * p[i], l, u);
+                    const double gi = g[i] - alpha * hp[i];
+                    g[i] = gi;
+                    const Split sp = split(xi, gi, l, u, abar);
+                    if (kind == STEP_EXPAND) {
+                        xi = clampd(xi - abar * sp.phi, l, u);
+                    } else {
+                        us[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+                        us[1] += sp.beta * sp.beta;
+                        us[2] += sp.phit * sp.phi;
+                        us[3] += sp.phi * hp[i];
+                    }
+                    xt[i] = xi;
+                }
+                ++inner;
+                if (kind == STEP_EXPAND) {
+                    __syncthreads();
+                    us[0] = us[1] = us[2] = 0.0;
+                    for (int i = tid; i < n; i += TPB) {
+                        const double xi = xt[i];
+                        const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - rhs[i];
+                        g[i] = gi;
+                        const Split sp = split(xi, gi, lv[i], uv[i], abar);
+                        us[0] += sp.phi * sp.phi + sp.beta * sp.beta;
+                        us[1] += sp.beta * sp.beta;
+                        us[2] += sp.phit * sp.phi;
+                    }
+                }
+                wg_reduce<4, 0u>(us, lds);
+                if (kind == STEP_CG) gam = us[3] / hs[0];
+                last = kind;
+                done = sqrt(us[0]) <= eps_use || inner >= P.max_inner;
+                const bool prop = us[1] <= P.mprgp_gamma * P.mprgp_gamma * us[2];
+                mode = !prop ? DIR_BETA : (last == STEP_CG ? DIR_CONJ : DIR_PHI);
+            }
+            inner_total += inner;
+            for (int i = tid; i < n; i += TPB) xbar[v0 + i] = 2.0 * xt[i] - x[i];
+            __syncthreads();
         }
-        __syncthreads();
         // ---- dual step and Halpern on y --------------------------------------------
         const double w = (double)(t + 1) / (double)(t + 2), wa = 1.0 / (double)(t + 2);
         const double th = P.theta;
@@ -324,6 +454,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         wg_reduce<7, kinds7>(a, lds);
         ndx2 = a[0];
         ndy2 = a[1];
+        if (P.eps_fixed <= 0.0) eps = fmin(eps, fmax(P.gamma_inner * omega * sqrt(ndx2) / tau, P.eps_min));
         if (store) {
             ytil_max = a[2]; ptil_sum = a[3]; ptil_abs = a[4];
             d_max = unb ? a[5] : 0.0;
@@ -339,6 +470,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         o.pad = 0;
         o.iterations = k;
         o.restarts = restarts;
+        o.inner_iterations = inner_total;
         o.r_primal = rp_; o.r_dual = rd_; o.r_gap = rg_;
         o.pobj = pobj; o.dobj = dobj; o.omega = omega;
         o.ytil_max = ytil_max; o.d_max = d_max;
@@ -367,10 +499,14 @@ int batch_grid(int count)
     return g < 1 ? 1 : g;
 }
 
-hipError_t launch_batch_norm(const BatchDev& B, double tol, long long max_iter, double* v,
-                             double* w, double* u, double* out, hipStream_t s)
+hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* coloff,
+                             const int* mrp, const int* mcol, const double* mval,
+                             const int* trp, const int* tcol, const double* tval, const int* sel,
+                             double tol, long long max_iter, double* v, double* w, double* u,
+                             double* out, hipStream_t s)
 {
-    k_batch_norm<<<batch_grid(B.count), TPB, 0, s>>>(B, tol, max_iter, v, w, u, out);
+    k_batch_norm<<<batch_grid(B.count), TPB, 0, s>>>(B.count, B.queue, rowoff, coloff, mrp, mcol, mval,
+                                                     trp, tcol, tval, sel, tol, max_iter, v, w, u, out);
     return hipGetLastError();
 }
 

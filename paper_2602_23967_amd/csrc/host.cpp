@@ -14,11 +14,12 @@
 #include <vector>
 
 #include "../../include/pdhcg.h"
+#include "host_internal.h"
 #include "pdhcg_internal.h"
 
 using namespace pdhcg;
 
-namespace {
+namespace pdhcg {
 
 thread_local std::string g_err;
 
@@ -125,6 +126,10 @@ int check_bounds(const char* name, int64_t len, const double* l, const double* u
     }
     return 0;
 }
+
+}  // namespace pdhcg
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // SpMV schedule: greedy row blocks of <= NNZ_CAP nonzeros and <= ROWS_CAP
@@ -848,6 +853,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     I.solve_seconds = t1 - t0;
     I.setup_seconds = h->setup_seconds;
     for (int f = 0; f < QP_NFAM; ++f) I.fam_launches[f] = h->fam_launches[f];
+    I.spmv_hp_active = r.hp_active;
     for (size_t i = 0; i < h->ev_used; ++i) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, h->ev_pool[i].ev[0], h->ev_pool[i].ev[1]) == hipSuccess) {
@@ -971,9 +977,10 @@ struct qp_batch {
     std::vector<int64_t> voff, roff;
     BatchDev B;
     hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    double t_launch = 0.0;
     std::vector<void*> allocs;
     std::vector<BatchOut> out;
-    double eta_unused = 0.0;
     std::vector<double> norm_A;
     int solved = 0;
     double setup_seconds = 0.0, solve_seconds = 0.0;
@@ -1013,6 +1020,7 @@ void qp_batch_destroy(qp_batch* bt)
     if (!bt) return;
     if (bt->stream) (void)hipStreamSynchronize(bt->stream);
     for (void* p : bt->allocs) (void)hipFree(p);
+    if (bt->done) (void)hipEventDestroy(bt->done);
     if (bt->stream) (void)hipStreamDestroy(bt->stream);
     delete bt;
 }
@@ -1062,13 +1070,21 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     }
     if ((rc = check_csr("A", m, n, Ap, Aj, Av))) return rc;
     std::vector<double> qd(n, 0.0);
+    std::vector<int> qgen(count, 0);
+    std::vector<int64_t> q_empty(n + 1, 0);
     if (Qp) {
         if ((rc = check_csr("Q", n, n, Qp, Qj, Qv))) return rc;
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) {
-                if (Qj[k] != i) return fail(QP_ERR_INVALID_ARG, "batched solve needs a diagonal Q");
-                qd[i] += Qv[k];
-            }
+        if ((rc = check_symmetric(n, Qp, Qj, Qv))) return rc;
+        for (int64_t b = 0; b < count; ++b)
+            for (int64_t i = var_off[b]; i < var_off[b + 1]; ++i)
+                for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) {
+                    if (Qj[k] < var_off[b] || Qj[k] >= var_off[b + 1])
+                        return fail(QP_ERR_INVALID_ARG, "Q is not block-diagonal at row " + std::to_string(i));
+                    if (Qj[k] != i) qgen[b] = 1;
+                    else qd[i] += Qv[k];
+                }
+    } else {
+        Qp = q_empty.data();
     }
     for (int64_t i = 0; i < count; ++i)
         for (int64_t r = row_off[i]; r < row_off[i + 1]; ++r)
@@ -1085,7 +1101,8 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     bt->m = m;
     bt->voff.assign(var_off, var_off + count + 1);
     bt->roff.assign(row_off, row_off + count + 1);
-    if (hipStreamCreate(&bt->stream) != hipSuccess) return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    if (hipStreamCreate(&bt->stream) != hipSuccess || hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
     BatchDev& B = bt->B;
     B.count = (int)count;
     std::vector<int> vo32(count + 1), ro32(count + 1), arp32(m + 1);
@@ -1095,9 +1112,12 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     std::vector<int32_t> tj;
     std::vector<double> tv;
     transpose(m, n, Ap, Aj, Av, tp, tj, tv);
-    std::vector<int> trp32(n + 1);
-    for (int64_t i = 0; i <= n; ++i) trp32[i] = (int)tp[i];
-    const int64_t nnz = Ap[m];
+    std::vector<int> trp32(n + 1), qrp32(n + 1);
+    for (int64_t i = 0; i <= n; ++i) { trp32[i] = (int)tp[i]; qrp32[i] = (int)Qp[i]; }
+    const int64_t nnz = Ap[m], qnnz = Qp[n];
+    if ((rc = bupload(bt, &B.qrp, qrp32.data(), qrp32.size())) || (rc = bupload(bt, &B.qcol, Qj, (size_t)qnnz)) ||
+        (rc = bupload(bt, &B.qval, Qv, (size_t)qnnz)))
+        return bail(rc);
     if ((rc = bupload(bt, &B.voff, vo32.data(), vo32.size())) || (rc = bupload(bt, &B.roff, ro32.data(), ro32.size())) ||
         (rc = bupload(bt, &B.arp, arp32.data(), arp32.size())) || (rc = bupload(bt, &B.acol, Aj, (size_t)nnz)) ||
         (rc = bupload(bt, &B.aval, Av, (size_t)nnz)) || (rc = bupload(bt, &B.trp, trp32.data(), trp32.size())) ||
@@ -1106,7 +1126,7 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
         (rc = bupload(bt, &B.lv, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv, uvv.data(), (size_t)n)) ||
         (rc = bupload(bt, &B.lc, lcv.data(), (size_t)m)) || (rc = bupload(bt, &B.uc, ucv.data(), (size_t)m)))
         return bail(rc);
-    double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d};
+    double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d, &B.rhs, &B.g, &B.p, &B.hp};
     for (double** p : nv)
         if ((rc = balloc(bt, p, (size_t)n))) return bail(rc);
     double** mv[] = {&B.y, &B.ya, &B.yt, &B.ytil};
@@ -1120,13 +1140,27 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     const qp_params dp = qp_params_default();
     if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemsetAsync failed"));
-    if (launch_batch_norm(B, dp.power_tol, dp.power_max_iter, B.x, B.y, B.xt, dnorm, bt->stream) != hipSuccess ||
+    if (launch_batch_norm(B, B.roff, B.voff, B.arp, B.acol, B.aval, B.trp, B.tcol, B.tval, nullptr,
+                          dp.power_tol, dp.power_max_iter, B.x, B.y, B.xt, dnorm, bt->stream) != hipSuccess ||
         hipStreamSynchronize(bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
     bt->norm_A.resize(count);
     if (hipMemcpy(bt->norm_A.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemcpy failed"));
-    std::vector<double> eta(count), om0(count), cmax(count), bsc(count), gq(count);
+    // ||Q_b||_2 for the instances with a non-diagonal Q (Q symmetric: Q' = Q)
+    std::vector<double> normq_raw(count, 0.0);
+    {
+        const int* dsel = nullptr;
+        if ((rc = bupload(bt, &dsel, qgen.data(), (size_t)count))) return bail(rc);
+        B.qgen = dsel;
+        if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess ||
+            launch_batch_norm(B, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
+                              dp.power_tol, dp.power_max_iter, B.x, B.xa, B.xt, dnorm, bt->stream) != hipSuccess ||
+            hipStreamSynchronize(bt->stream) != hipSuccess ||
+            hipMemcpy(normq_raw.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
+    }
+    std::vector<double> eta(count), om0(count), cmax(count), bsc(count), gq(count), nq(count);
     std::vector<int> unb(count, 0);
     for (int64_t i = 0; i < count; ++i) {
         const double na = bt->norm_A[i];
@@ -1138,12 +1172,17 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
             if (std::isfinite(lcv[r])) bl = std::max(bl, std::fabs(lcv[r]));
             if (std::isfinite(ucv[r])) bl = std::max(bl, std::fabs(ucv[r]));
         }
+        double qmax = 0.0;
         for (int64_t v = var_off[i]; v < var_off[i + 1]; ++v) {
             nc += c[v] * c[v];
             cm = std::max(cm, std::fabs(c[v]));
-            g = std::max(g, std::fabs(qd[v]));
+            double rs = 0.0;
+            for (int64_t k = Qp[v]; k < Qp[v + 1]; ++k) rs += std::fabs(Qv[k]);
+            g = std::max(g, rs);
+            qmax = std::max(qmax, std::fabs(qd[v]));
             if (!std::isfinite(lvv[v]) || !std::isfinite(uvv[v])) unb[i] = 1;
         }
+        nq[i] = qgen[i] ? dp.norm_safety * normq_raw[i] : qmax;
         nb = std::sqrt(nb);
         nc = std::sqrt(nc);
         om0[i] = (nc > 1e-10 && nb > 1e-10) ? nc / nb : 1.0;
@@ -1153,7 +1192,8 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     }
     if ((rc = bupload(bt, &B.eta, eta.data(), (size_t)count)) || (rc = bupload(bt, &B.omega0, om0.data(), (size_t)count)) ||
         (rc = bupload(bt, &B.cmax, cmax.data(), (size_t)count)) || (rc = bupload(bt, &B.bscale, bsc.data(), (size_t)count)) ||
-        (rc = bupload(bt, &B.gammaq, gq.data(), (size_t)count)) || (rc = bupload(bt, &B.unb, unb.data(), (size_t)count)))
+        (rc = bupload(bt, &B.gammaq, gq.data(), (size_t)count)) || (rc = bupload(bt, &B.unb, unb.data(), (size_t)count)) ||
+        (rc = bupload(bt, &B.normq, nq.data(), (size_t)count)))
         return bail(rc);
     bt->setup_seconds = now_s() - t0;
     *out = bt;
@@ -1161,7 +1201,11 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     return 0;
 }
 
-int qp_batch_solve(qp_batch* bt, const qp_params* params)
+}  // extern "C"
+
+namespace pdhcg {
+
+int batch_launch(qp_batch* bt, const qp_params* params)
 {
     if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
     const qp_params p = params ? *params : qp_params_default();
@@ -1171,18 +1215,49 @@ int qp_batch_solve(qp_batch* bt, const qp_params* params)
     P.kp = p.kp; P.ki = p.ki; P.kd = p.kd;
     P.rs_suff = p.restart_sufficient; P.rs_nec = p.restart_necessary; P.rs_art = p.restart_artificial;
     P.max_iter = p.max_iter; P.check_every = p.check_every; P.use_halpern = p.use_halpern;
-    const double t0 = now_s();
+    P.gamma_inner = p.gamma_inner; P.eps_min = p.eps_min; P.eps_fixed = p.eps_inner_fixed;
+    P.mprgp_gamma = p.mprgp_gamma; P.abar_scale = p.mprgp_abar_scale; P.max_inner = p.max_inner;
+    bt->t_launch = now_s();
     HIPCHK(hipMemsetAsync(bt->B.queue, 0, sizeof(int), bt->stream));
     HIPCHK(launch_batch_solve(bt->B, P, bt->stream));
-    HIPCHK(hipStreamSynchronize(bt->stream));
-    bt->solve_seconds = now_s() - t0;
+    HIPCHK(hipEventRecord(bt->done, bt->stream));
+    return 0;
+}
+
+// 1 when the launched solve has finished, 0 while it runs, < 0 on error
+int batch_poll(qp_batch* bt)
+{
+    const hipError_t q = hipEventQuery(bt->done);
+    if (q == hipSuccess) return 1;
+    if (q == hipErrorNotReady) return 0;
+    return fail(QP_ERR_DEVICE, std::string("batch solve failed: ") + hipGetErrorString(q));
+}
+
+// waits for the launched solve and fetches the per-instance outcomes;
+// returns the number of OPTIMAL instances
+int batch_finish(qp_batch* bt)
+{
+    HIPCHK(hipEventSynchronize(bt->done));
+    bt->solve_seconds = now_s() - bt->t_launch;
     bt->out.resize(bt->count);
     HIPCHK(hipMemcpy(bt->out.data(), bt->B.out, sizeof(BatchOut) * bt->count, hipMemcpyDeviceToHost));
     bt->solved = 1;
     int opt = 0;
     for (const BatchOut& o : bt->out) opt += o.status == QP_OPTIMAL;
-    g_err.clear();
     return opt;
+}
+
+}  // namespace pdhcg
+
+extern "C" {
+
+int qp_batch_solve(qp_batch* bt, const qp_params* params)
+{
+    int rc = batch_launch(bt, params);
+    if (rc < 0) return rc;
+    rc = batch_finish(bt);
+    if (rc >= 0) g_err.clear();
+    return rc;
 }
 
 int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info* info)
@@ -1212,6 +1287,7 @@ int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info
         info->status = o.status;
         info->iterations = o.iterations;
         info->restarts = o.restarts;
+        info->inner_iterations = o.inner_iterations;
         info->r_primal = o.r_primal;
         info->r_dual = o.r_dual;
         info->r_gap = o.r_gap;

@@ -426,6 +426,7 @@ struct EpiStepA : EpiBase {
     __device__ void finalize(const double* t) const
     {
         Ctrl* c = ctrl;
+        c->hp_active += 1;
         if (ng) {
             c->need_g = 0;
             c->skip_update = 1;

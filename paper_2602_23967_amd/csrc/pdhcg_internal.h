@@ -73,6 +73,7 @@ struct Ctrl {
     double gp2, b2, ptp;           // ||g^P||^2, ||beta||^2, phit'phi at the current x
     double res;                    // ||g^P|| at the last decision
     long long inner_it, inner_total, max_inner;
+    long long hp_active;           // launches of the inner product that did the product
     int done, need_g, skip_update, dir_mode, last_step, step_kind, proportional, pad0;
     // outer state (Sections 3.1-3.2)
     long long k, t, restarts, checks, max_iter;
@@ -155,13 +156,14 @@ constexpr int BATCH_GRID_MAX = 2048;   // persistent workgroups (instances are q
 
 struct BatchOut {
     int status, pad;
-    long long iterations, restarts;
+    long long iterations, restarts, inner_iterations;
     double r_primal, r_dual, r_gap, pobj, dobj, omega, ytil_max, d_max;
 };
 
 struct BatchParams {
     double tol, eps_inf, theta, kp, ki, kd, rs_suff, rs_nec, rs_art;
-    long long max_iter, check_every;
+    double gamma_inner, eps_min, eps_fixed, mprgp_gamma, abar_scale;
+    long long max_iter, check_every, max_inner;
     int use_halpern, pad;
 };
 
@@ -173,19 +175,30 @@ struct BatchDev {
     const double* aval = nullptr;
     const int *trp = nullptr, *tcol = nullptr;  // A'
     const double* tval = nullptr;
+    const int *qrp = nullptr, *qcol = nullptr;  // Q (block-diagonal, global indices)
+    const double* qval = nullptr;
     const double *qd = nullptr, *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
     // per instance
     const double *eta = nullptr, *omega0 = nullptr, *cmax = nullptr, *bscale = nullptr, *gammaq = nullptr;
+    const double* normq = nullptr;              // ||Q_b||_2 (x 1.01 for a non-diagonal Q_b)
     const int* unb = nullptr;
+    const int* qgen = nullptr;                  // 1: Q_b not diagonal (inner CG solve)
     // state (packed like the problem)
     double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
     double *xbar = nullptr, *aty = nullptr, *d = nullptr, *ytil = nullptr;
+    double *rhs = nullptr, *g = nullptr, *p = nullptr, *hp = nullptr;
     BatchOut* out = nullptr;
 };
 
 int batch_grid(int count);
-hipError_t launch_batch_norm(const BatchDev& B, double tol, long long max_iter, double* v,
-                             double* w, double* u, double* out, hipStream_t s);
+// ||M_b||_2 per instance by power iteration on M_b'M_b: M (rows given by
+// rowoff, columns by coloff) and its transpose Mt; instances with sel[b] == 0
+// get 0 (sel may be NULL)
+hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* coloff,
+                             const int* mrp, const int* mcol, const double* mval,
+                             const int* trp, const int* tcol, const double* tval, const int* sel,
+                             double tol, long long max_iter, double* v, double* w, double* u,
+                             double* out, hipStream_t s);
 hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s);
 
 }  // namespace pdhcg

@@ -169,8 +169,10 @@ def test_batch_validation_errors():
     _bad(mk(vo=vo2), P.ERR_INVALID_ARG)                       # empty instance
     A2 = big.A.tolil(); A2[0, int(vo[1]) + 1] = 1.0           # entry outside its block
     _bad(mk(A=A2.tocsr()), P.ERR_INVALID_ARG)
-    Qn = big.Q.tolil(); Qn[0, 1] = 0.5; Qn[1, 0] = 0.5        # non-diagonal Q
+    Qn = big.Q.tolil(); Qn[0, int(vo[1])] = 0.5; Qn[int(vo[1]), 0] = 0.5   # Q entry across blocks
     _bad(mk(Q=Qn.tocsr()), P.ERR_INVALID_ARG)
+    Qs = big.Q.tolil(); Qs[0, 1] = 0.5                          # Q not symmetric
+    _bad(mk(Q=Qs.tocsr()), P.ERR_NOT_SYMMETRIC)
     try:
         h = mk()()
     except P.QPError as e:

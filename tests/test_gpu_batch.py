@@ -39,6 +39,9 @@ def mix():
     qs = [I.mpc(i) for i in range(20)]
     qs += [I.mpc(100, infeasible=True), I.mpc(101, infeasible=True)]
     qs += [I.portfolio(5, n_assets=3000, k_factors=20), I.tiny_lp(3), _unbounded_lp()]
+    # non-diagonal Q: the inner boxed-CG solve runs inside the workgroup
+    qs += [I.random_small(0), I.random_small(1, n=300), I.mixed_bounds(0), I.tiny(3, n=6, m=3),
+           I.contradictory_rows(0), I.unbounded_qp(0)]
     return qs
 
 
@@ -68,10 +71,11 @@ def test_batch_matches_oracle(torch, mix):
 def test_batch_alone_equals_in_the_mix(torch, mix):
     """An instance's result does not depend on the other instances of the
     launch (bitwise)."""
+    picks = (3, 7, 21, 25, 27)
     with P.BatchSolver(mix) as bs:
         bs.solve()
-        together = [bs.result(i) for i in (3, 7, 21)]
-    for i, g in zip((3, 7, 21), together):
+        together = [bs.result(i) for i in picks]
+    for i, g in zip(picks, together):
         with P.BatchSolver([mix[i]]) as one:
             one.solve()
             a = one.result(0)
@@ -118,3 +122,15 @@ def test_batch_many_instances(torch):
             g = bs.result(i)
             k = oracle.kkt(qs[i], g.x, g.y)
             assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6
+
+
+def test_batch_general_q_matches_single_path(torch):
+    q = I.random_small(2)
+    with P.BatchSolver([q]) as bs:
+        bs.solve()
+        gb = bs.result(0)
+    with P.Solver(q) as s:
+        gs = s.solve()
+    assert gb.status == gs.status == P.OPTIMAL
+    assert gb.info["inner_iterations"] > 0
+    assert gb.info["primal_obj"] == pytest.approx(gs.info["primal_obj"], rel=1e-6)
