@@ -82,13 +82,14 @@ def cpu_baseline(q, gpu_units_per_solve, sample_iters):
     }
 
 
-def batch_bytes(q, iters):
+def batch_bytes(q, iters, vb=12):
     """Algorithmic bytes of one instance's iterations in the batched kernel:
-    the A and A' products (12 B per nonzero each, int32 row pointers),
+    the A and A' products (vb B per nonzero each: 12 in FP64, 8 with FP32
+    values; int32 row pointers),
     the primal step (x, c, q, l_v, u_v read; x_T, x_bar written), the dual
     step (x_bar gathered once; y, y anchor, l_c, u_c read; y_T, y written)
     and the Halpern step on x (x_T, x, anchor read; x written)."""
-    per_iter = 24 * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * (7 + 1 + 4) + 8 * q.m * 6
+    per_iter = 2 * vb * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * (7 + 1 + 4) + 8 * q.m * 6
     return per_iter * iters
 
 
@@ -98,7 +99,9 @@ def main_batch(args, torch, P, I):
     log(f"generated {len(qs)} MPC instances in {time.perf_counter() - t:.1f}s "
         f"(n {sum(q.n for q in qs)}, m {sum(q.m for q in qs)}, nnz(A) {sum(q.nnz_A for q in qs)})")
     bs = P.BatchSolver(qs)
-    params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
+    mixed = args.precision == "mixed"
+    params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter,
+                                 precision=P.PRECISION_MIXED if mixed else P.PRECISION_FP64)
     for w in range(args.warmup):
         st, sec = bs.solve(params)
         log(f"warmup {w}: {int(np.sum(st == P.OPTIMAL))}/{len(qs)} optimal in {sec * 1e3:.1f} ms")
@@ -114,14 +117,15 @@ def main_batch(args, torch, P, I):
     elapsed = time.perf_counter() - t_start
     infos = [bs.result(i).info for i in range(len(qs))]
     iters = [i["iterations"] for i in infos]
-    nbytes = sum(batch_bytes(q, it) for q, it in zip(qs, iters))
+    nbytes = sum(batch_bytes(q, it, 8 if mixed else 12) for q, it in zip(qs, iters))
     kernel_s = float(np.median(lat))
     bs.close()
     # the same instances one at a time through the single-QP path, FP64
     one = []
+    p64 = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
     for q in qs[: args.one_at_a_time]:
         with P.Solver(q) as s1:
-            r = s1.solve(params)
+            r = s1.solve(p64)
             one.append(r.info["solve_seconds"])
     out = {
         "metric": METRIC,
@@ -130,9 +134,10 @@ def main_batch(args, torch, P, I):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f32 products + f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"batched linear MPC, {len(qs)} instances, horizon T ~ U{{10..50}}, "
-                               f"12 states, 4 inputs, one persistent launch, tol {args.tol:g}",
+                               f"12 states, 4 inputs, one persistent launch, tol {args.tol:g}, "
+                               f"{'mixed precision' if mixed else 'FP64'}",
                    "instances": len(qs)},
         "solved": bool(np.all(st == P.OPTIMAL)),
         "iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
@@ -156,6 +161,98 @@ def main_batch(args, torch, P, I):
     print(json.dumps(out), flush=True)
 
 
+def portfolio_bytes(q, fam, vb):
+    """Algorithmic bytes of one launch of the diagonal-Q path's two products
+    (vb = bytes per nonzero: 12 in FP64, 8 with FP32 values and int32
+    columns).  rhs: A'y fused with the closed-form primal step -- the
+    nonzeros, row pointers, y gathered once, x, c, q, l_v, u_v read, x_T and
+    x_bar written.  dual: A x_bar fused with the dual step and Halpern on y --
+    the nonzeros, row pointers, x_bar gathered once, y, y anchor, l_c, u_c
+    read, y_T and y written."""
+    if fam == "rhs":
+        return vb * q.nnz_A + 4 * (q.n + 1) + 8 * q.m + 8 * q.n * 7
+    return vb * q.nnz_A + 4 * (q.m + 1) + 8 * q.n + 8 * q.m * 6
+
+
+def main_portfolio(args, torch, P, I):
+    t = time.perf_counter()
+    q = I.portfolio(0)
+    log(f"generated {q.name}: n={q.n} m={q.m} nnz(A)={q.nnz_A} in {time.perf_counter() - t:.1f}s")
+    mixed = args.precision == "mixed"
+    prec = P.PRECISION_MIXED if mixed else P.PRECISION_FP64
+    h = P.qp_create_from(q)
+    params = P.qp_params_default(tol=args.tol, timing=args.timing, max_iter=args.max_iter, precision=prec)
+    try:
+        for w in range(args.warmup):
+            st = P.qp_solve_ex(h, params)
+            log(f"warmup {w}: {P.STATUS_NAMES[st]}")
+        torch.cuda.synchronize()
+        lat, infos = [], []
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            a = time.perf_counter()
+            st = P.qp_solve_ex(h, params)
+            lat.append(time.perf_counter() - a)
+            _, x, y, info = P.qp_result(h, q.n, q.m)
+            infos.append(info)
+            log(f"step {s_}: {P.STATUS_NAMES[st]} {lat[-1] * 1e3:.1f} ms it={info['iterations']}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        # the plain FP64 form on the same GPU, and the result's error against it
+        p64 = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
+        a = time.perf_counter()
+        P.qp_solve_ex(h, p64)
+        t64 = time.perf_counter() - a
+        _, x64, _, i64 = P.qp_result(h, q.n, q.m)
+    finally:
+        P.qp_destroy(h)
+    solved = all(i["status"] == P.OPTIMAL and max(i["r_primal"], i["r_dual"], i["r_gap"]) <= args.tol
+                 for i in infos)
+    vb = 8 if mixed else 12
+    fams = {}
+    for name in ("rhs", "dual"):
+        j = P.FAMILIES.index(name)
+        tj = sum(i["fam_timed"][j] for i in infos)
+        fams[name] = (1e3 * sum(i["fam_ms"][j] for i in infos) / max(tj, 1), tj,
+                      infos[-1]["fam_launches"][j])
+    dom = max(fams, key=lambda k: fams[k][0] * fams[k][2])
+    avg_us = fams[dom][0]
+    nbytes = portfolio_bytes(q, dom, vb)
+    achieved = nbytes / (avg_us * 1e-6) / 1e9 if fams[dom][1] else None
+    f, f64 = infos[-1]["primal_obj"], i64["primal_obj"]
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "QPs solved/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 products + f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"factor-model portfolio, {q.n - 1000} assets + 1000 factors, "
+                               f"m={q.m}, diagonal Q, tol {args.tol:g}, "
+                               f"{'mixed precision' if mixed else 'FP64'}",
+                   "n": q.n, "m": q.m, "nnz_A": q.nnz_A, "tol": args.tol},
+        "solved": solved,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "iterations": {"outer": infos[-1]["iterations"],
+                       "outer_per_s": infos[-1]["iterations"] / np.median(lat)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": {"rhs": "A'y + closed-form primal step (k_spmv<EpiProx>)",
+                                "dual": "A x_bar + dual step + Halpern on y (k_spmv<EpiDual>)"}[dom],
+                     "bytes_per_launch": nbytes, "avg_us": avg_us},
+        "kernels": {k: {"avg_us": round(v[0], 3), "launches_per_solve": v[2]} for k, v in fams.items()},
+        "fp64_plain": {"value": 1.0 / t64, "unit": "QPs solved/s", "iterations": i64["iterations"],
+                       "status": P.STATUS_NAMES[i64["status"]]},
+        "error_vs_fp64": {"objective_rel": abs(f - f64) / (1 + abs(f64)),
+                          "x_inf": float(np.abs(x - x64).max())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(q, infos[-1]["iterations"], args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,7 +264,10 @@ def main():
     ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
     ap.add_argument("--max-iter", type=int, default=100000,
                     help="outer iteration cap (lower only for short profiling runs)")
-    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch"], default="large_sparse")
+    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch", "portfolio"], default="large_sparse")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="arithmetic of the portfolio and batched workloads (default: mixed for them; "
+                         "the large sparse workload is FP64)")
     ap.add_argument("--count", type=int, default=4096, help="instances of the batched workload")
     ap.add_argument("--one-at-a-time", type=int, default=32,
                     help="instances of the batched workload also solved one by one")
@@ -199,7 +299,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "mpc_batch":
+        if args.precision is None:
+            args.precision = "mixed"
         return main_batch(args, torch, P, I)
+    if args.workload == "portfolio":
+        if args.precision is None:
+            args.precision = "mixed"
+        return main_portfolio(args, torch, P, I)
 
     t = time.perf_counter()
     q = I.large_sparse(0, n=args.n)

@@ -84,8 +84,17 @@ typedef struct {
     double mprgp_gamma;       /* proportioning constant of the inner solver; 1 */
     double mprgp_abar_scale;  /* expansion step = scale / (||Q||_2 + 1/tau); 1.9 */
     int timing;               /* > 0: time every `timing`-th launch of each kernel family */
-    int reserved;
+    int precision;            /* QP_PRECISION_FP64 (0, default) or QP_PRECISION_MIXED (1) */
 } qp_params;
+
+/* Arithmetic of a solve.  FP64: every step in double precision.  MIXED: the
+ * sparse products of the iteration itself (A'y with the primal step, A x_bar
+ * with the dual step, the products with Q of the inner solve) read an FP32
+ * copy of the matrix values, round the gathered operand to FP32 and sum in
+ * FP32; the vector updates, the Halpern anchor and averages, the step sizes,
+ * the KKT residuals (Section 4), the restart / termination tests and the
+ * certificates (Section 5) stay FP64, and the checks use the FP64 values. */
+enum { QP_PRECISION_FP64 = 0, QP_PRECISION_MIXED = 1 };
 
 /* kernel families reported by qp_info.fam_* when timing is on */
 enum {
@@ -102,7 +111,7 @@ enum {
 
 typedef struct {
     int status;
-    int reserved;
+    int precision;             /* QP_PRECISION_* the solve ran in */
     int64_t iterations;        /* outer iterations */
     int64_t inner_iterations;  /* total inner (CG/MPRGP) iterations */
     int64_t restarts;

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "PRIMAL_INFEASIBLE", 3: "DUAL_
                 4: "ITERATION_LIMIT", 5: "NUMERICAL_ERROR"}
 ERR_INVALID_ARG, ERR_NOT_SYMMETRIC, ERR_DEVICE, ERR_STATE = -1, -2, -3, -4
 OP_Q, OP_A, OP_AT = 0, 1, 2
+PRECISION_FP64, PRECISION_MIXED = 0, 1
 FAMILIES = ["spmv_hp", "update", "dir", "rhs", "ginit", "dual", "halpx", "check"]
 NFAM = len(FAMILIES)
 
@@ -44,11 +45,11 @@ class QPParams(C.Structure):
                 ("eps_inf", C.c_double), ("eta_scale", C.c_double), ("norm_safety", C.c_double),
                 ("power_tol", C.c_double), ("power_max_iter", _i64),
                 ("mprgp_gamma", C.c_double), ("mprgp_abar_scale", C.c_double),
-                ("timing", C.c_int), ("reserved", C.c_int)]
+                ("timing", C.c_int), ("precision", C.c_int)]
 
 
 class QPInfo(C.Structure):
-    _fields_ = [("status", C.c_int), ("reserved", C.c_int), ("iterations", _i64),
+    _fields_ = [("status", C.c_int), ("precision", C.c_int), ("iterations", _i64),
                 ("inner_iterations", _i64), ("restarts", _i64), ("checks", _i64),
                 ("r_primal", C.c_double), ("r_dual", C.c_double), ("r_gap", C.c_double),
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double),

@@ -90,6 +90,21 @@ __device__ __forceinline__ double row_dot(const int* rp, const int* col, const d
     return s;
 }
 
+// a bulk product of the iteration: FP32 values, operand rounded to FP32 and
+// an FP32 sum in mixed precision, else the FP64 row_dot
+template <bool F32>
+__device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, const double* val,
+                                               const float* val32, const double* x, int row)
+{
+    if constexpr (F32) {
+        float s = 0.0f;
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)x[col[q]];
+        return (double)s;
+    } else {
+        return row_dot(rp, col, val, x, row);
+    }
+}
+
 // ---- ||M_b||_2 by power iteration on M_b'M_b, one instance per workgroup ----
 __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const int* rowoff,
                                                    const int* coloff, const int* mrp,
@@ -161,6 +176,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
 
 // ---- the solve -----------------------------------------------------------------
 
+template <bool F32>
 __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds)
 {
     const int v0 = B.voff[b], n = B.voff[b + 1] - v0;
@@ -317,7 +333,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         if (!qgen) {
             // ---- primal step: closed form (Section 2.2) and x_bar -----------------
             for (int i = tid; i < n; i += TPB) {
-                const double s = row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
+                const double s = row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, v0 + i);
                 const double xi = x[i];
                 const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
                 xt[i] = v;
@@ -329,10 +345,10 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             const double abar = P.abar_scale / (normq + it);
             double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
             for (int i = tid; i < n; i += TPB) {
-                const double r = x[i] * it - c[i] - row_dot(B.trp, B.tcol, B.tval, B.y, v0 + i);
+                const double r = x[i] * it - c[i] - row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, v0 + i);
                 rhs[i] = r;
                 const double xi = xt[i];
-                const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - r;
+                const double gi = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.xt, v0 + i) + it * xi - r;
                 g[i] = gi;
                 const Split sp = split(xi, gi, lv[i], uv[i], abar);
                 st[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -356,7 +372,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 double hs[3] = {0.0, 0.0, INFINITY};   // p'Hp, g'p, feasible step
                 for (int i = tid; i < n; i += TPB) {
                     const double pi = p[i], xi = xt[i];
-                    const double h = row_dot(B.qrp, B.qcol, B.qval, B.p, v0 + i) + it * pi;
+                    const double h = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i) + it * pi;
                     hp[i] = h;
                     hs[0] += pi * h;
                     hs[1] += g[i] * pi;
@@ -397,7 +413,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     us[0] = us[1] = us[2] = 0.0;
                     for (int i = tid; i < n; i += TPB) {
                         const double xi = xt[i];
-                        const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - rhs[i];
+                        const double gi = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.xt, v0 + i) + it * xi - rhs[i];
                         g[i] = gi;
                         const Split sp = split(xi, gi, lv[i], uv[i], abar);
                         us[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -422,7 +438,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         double a[7] = {0, 0, 0, 0, 0, 0, 0};
         constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
         for (int j = tid; j < m; j += TPB) {
-            const double s = row_dot(B.arp, B.acol, B.aval, xbar, r0 + j);
+            const double s = row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, r0 + j);
             const double yj = y[j], l = lc[j], u = uc[j];
             const double v = yj / sigma + s;
             const double ytj = sigma * (v - clampd(v, l, u));
@@ -479,6 +495,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     __syncthreads();
 }
 
+template <bool F32>
 __global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
 {
     __shared__ double lds[16 * (TPB / 64)];
@@ -489,7 +506,7 @@ __global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
         const int b = s_b;
         __syncthreads();
         if (b >= B.count) return;
-        batch_solve_one(B, P, b, lds);
+        batch_solve_one<F32>(B, P, b, lds);
     }
 }
 
@@ -512,7 +529,8 @@ hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* co
 
 hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s)
 {
-    k_batch_solve<<<batch_grid(B.count), TPB, 0, s>>>(B, P);
+    if (B.aval32) k_batch_solve<true><<<batch_grid(B.count), TPB, 0, s>>>(B, P);
+    else k_batch_solve<false><<<batch_grid(B.count), TPB, 0, s>>>(B, P);
     return hipGetLastError();
 }
 

@@ -261,6 +261,8 @@ struct qp_handle {
     size_t ev_used = 0;
     int timing = 0;
     int64_t fam_launches[QP_NFAM] = {};
+    // FP32 copies of the matrix values, made at the first mixed-precision solve
+    float *val32_A = nullptr, *val32_AT = nullptr, *val32_Q = nullptr;
 };
 
 namespace {
@@ -281,6 +283,28 @@ int dalloc(qp_handle* h, T** p, size_t count)
     if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     h->dev_allocs.push_back(q);
     *p = static_cast<T*>(q);
+    return 0;
+}
+
+// the bulk products (not the checks) read FP32 values when the solve is in
+// mixed precision; the copies are made once and kept for later solves
+int set_precision(qp_handle* h, int precision)
+{
+    DevState& S = h->S;
+    if (precision == QP_PRECISION_MIXED) {
+        struct Item { CsrDev* M; float** keep; } items[3] = {{&S.A, &h->val32_A}, {&S.AT, &h->val32_AT},
+                                                            {&S.Q, &h->val32_Q}};
+        for (Item& it : items) {
+            if (it.M->nnz == 0 || !it.M->val) continue;
+            if (!*it.keep) {
+                if (int rc = dalloc(h, it.keep, (size_t)it.M->nnz)) return rc;
+                HIPCHK(launch_to_f32(it.M->val, *it.keep, it.M->nnz, h->stream));
+            }
+            it.M->val32 = *it.keep;
+        }
+    } else {
+        S.A.val32 = S.AT.val32 = S.Q.val32 = nullptr;
+    }
     return 0;
 }
 
@@ -751,11 +775,13 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
 {
     if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
     const qp_params p = params ? *params : qp_params_default();
-    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 || p.max_inner < 0 || p.inner_lag < 0)
+    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 || p.max_inner < 0 || p.inner_lag < 0 ||
+        (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))
         return fail(QP_ERR_INVALID_ARG, "invalid parameters");
     DevState& S = h->S;
     hipStream_t s = h->stream;
     const double t0 = now_s();
+    if (int rc = set_precision(h, p.precision)) return rc;
 
     h->timing = p.timing;
     std::fill(h->fam_launches, h->fam_launches + QP_NFAM, 0);
@@ -835,6 +861,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     qp_info& I = h->info;
     std::memset(&I, 0, sizeof(I));
     I.status = status;
+    I.precision = p.precision;
     I.iterations = r.k;
     I.inner_iterations = r.inner_total;
     I.restarts = r.restarts;
@@ -979,6 +1006,8 @@ struct qp_batch {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     double t_launch = 0.0;
+    int64_t nnz_a = 0, nnz_q = 0;
+    float *a32 = nullptr, *t32 = nullptr, *q32 = nullptr;   // made at the first mixed solve
     std::vector<void*> allocs;
     std::vector<BatchOut> out;
     std::vector<double> norm_A;
@@ -1115,6 +1144,8 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     std::vector<int> trp32(n + 1), qrp32(n + 1);
     for (int64_t i = 0; i <= n; ++i) { trp32[i] = (int)tp[i]; qrp32[i] = (int)Qp[i]; }
     const int64_t nnz = Ap[m], qnnz = Qp[n];
+    bt->nnz_a = nnz;
+    bt->nnz_q = qnnz;
     if ((rc = bupload(bt, &B.qrp, qrp32.data(), qrp32.size())) || (rc = bupload(bt, &B.qcol, Qj, (size_t)qnnz)) ||
         (rc = bupload(bt, &B.qval, Qv, (size_t)qnnz)))
         return bail(rc);
@@ -1209,7 +1240,23 @@ int batch_launch(qp_batch* bt, const qp_params* params)
 {
     if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
     const qp_params p = params ? *params : qp_params_default();
-    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1) return fail(QP_ERR_INVALID_ARG, "invalid parameters");
+    if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 ||
+        (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))
+        return fail(QP_ERR_INVALID_ARG, "invalid parameters");
+    if (p.precision == QP_PRECISION_MIXED) {
+        if (!bt->a32) {
+            int rc;
+            if ((rc = balloc(bt, &bt->a32, (size_t)bt->nnz_a)) || (rc = balloc(bt, &bt->t32, (size_t)bt->nnz_a)) ||
+                (rc = balloc(bt, &bt->q32, (size_t)bt->nnz_q)))
+                return rc;
+            HIPCHK(launch_to_f32(bt->B.aval, bt->a32, bt->nnz_a, bt->stream));
+            HIPCHK(launch_to_f32(bt->B.tval, bt->t32, bt->nnz_a, bt->stream));
+            HIPCHK(launch_to_f32(bt->B.qval, bt->q32, bt->nnz_q, bt->stream));
+        }
+        bt->B.aval32 = bt->a32; bt->B.tval32 = bt->t32; bt->B.qval32 = bt->q32;
+    } else {
+        bt->B.aval32 = bt->B.tval32 = bt->B.qval32 = nullptr;
+    }
     BatchParams P{};
     P.tol = p.tol; P.eps_inf = p.eps_inf; P.theta = p.theta;
     P.kp = p.kp; P.ki = p.ki; P.kd = p.kd;

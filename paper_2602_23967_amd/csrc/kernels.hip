@@ -20,6 +20,8 @@
 // atomics, so every result is reproducible.
 #include <math.h>
 
+#include <type_traits>
+
 #include "device_math.h"
 #include "pdhcg_internal.h"
 
@@ -64,11 +66,15 @@ struct SumOne {
 // the two kernel shapes
 // ---------------------------------------------------------------------------
 
-template <class E>
+// F32: products and row sums in single precision from the FP32 copy of the
+// values (the operand is rounded to FP32 as it is gathered); the row sum is
+// widened to FP64 before the epilogue, which keeps its arithmetic in FP64
+template <class E, bool F32>
 __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
 {
+    using T = typename std::conditional<F32, float, double>::type;
     constexpr int NR = E::NR > 0 ? E::NR : 1;
-    __shared__ double prod[NNZ_CAP];
+    __shared__ T prod[NNZ_CAP];
     __shared__ int srp[PART_ROWS_CAP + 1];   // the block's row pointers, relative to k0
     __shared__ double lds[NR * (TPB / 64)];
     E e = epi;
@@ -85,18 +91,21 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
         for (int r = threadIdx.x; r <= d.nrows; r += TPB) srp[r] = rp[r] - d.k0;
     }
     {
+        const T* val;
+        if constexpr (F32) val = M.val32;
+        else val = M.val;
         int cj[NNZ_CAP / TPB];
-        double av[NNZ_CAP / TPB];
+        T av[NNZ_CAP / TPB];
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
             cj[i] = q < cnt ? M.col[d.k0 + q] : -1;
-            av[i] = q < cnt ? M.val[d.k0 + q] : 0.0;
+            av[i] = q < cnt ? val[d.k0 + q] : T(0);
         }
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
-            if (cj[i] >= 0) prod[q] = av[i] * e.xval(cj[i]);
+            if (cj[i] >= 0) prod[q] = av[i] * static_cast<T>(e.xval(cj[i]));
         }
     }
     __syncthreads();
@@ -109,17 +118,18 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
         for (int r = grp; r < d.nrows; r += TPB / G) {
             const int row = d.row0 + r;
             const int a = srp[r], b = srp[r + 1];
-            double s = 0.0;
+            T s = T(0);
             for (int i = a + lane; i < b; i += G) s += prod[i];
             for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
             if (lane == 0) {
-                if (partial) M.ypart[(size_t)d.lr * M.rows + row] = s;
-                else e.row(row, s, acc);
+                if (partial) M.ypart[(size_t)d.lr * M.rows + row] = (double)s;
+                else e.row(row, (double)s, acc);
             }
         }
     } else if (d.nseg > 0) {
-        double s[1] = {0.0};
-        for (int q = threadIdx.x; q < cnt; q += TPB) s[0] += prod[q];
+        T ts = T(0);
+        for (int q = threadIdx.x; q < cnt; q += TPB) ts += prod[q];
+        double s[1] = {(double)ts};
         block_reduce<SumOne>(s, lds);
         if (threadIdx.x == 0) M.seg_part[d.seg_base + d.seg] = s[0];
     }
@@ -239,6 +249,9 @@ __global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double
 // ---------------------------------------------------------------------------
 
 struct EpiBase {
+    // true for the products of the iteration proper (not the checks): these
+    // run from the FP32 copy of the matrix when the solve is in mixed precision
+    static constexpr bool BULK = false;
     Ctrl* ctrl;
     __device__ bool skip() const { return false; }
     __device__ void init() {}
@@ -268,6 +281,7 @@ __device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long lo
 // primal step, diagonal Q (Section 2.2 closed form), fused into A'y:
 //   x_T = clip((x/tau - c - A'y) / (q + 1/tau), l_v, u_v)
 struct EpiProx : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 0;
     const double *y, *x, *c, *qd, *lv, *uv;
     double *xt, *xbar;
@@ -301,6 +315,7 @@ struct EpiClip : EpiBase {
 
 // rhs of the primal subproblem (eq. primal_update): rhs = x/tau - c - A'y
 struct EpiRhs : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 0;
     const double *y, *x, *c;
     double* rhs;
@@ -315,6 +330,7 @@ struct EpiRhs : EpiBase {
 // (tau', rhs' its step and right-hand side), so the new gradient is
 // g + (rhs' - rhs) + x_T (1/tau - 1/tau'); split statistics as in EpiGinit
 struct EpiRhsGrad : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 3;
     const double *y, *x, *c, *xt, *lv, *uv;
     double *rhs, *g;
@@ -355,6 +371,7 @@ struct EpiRhsGrad : EpiBase {
 // gradient of the subproblem at the warm start (feasible): g = Q x + x/tau - rhs,
 // with split statistics; finalize starts the inner solve
 struct EpiGinit : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 3;
     const double* xt;
     const double *rhs, *lv, *uv;
@@ -390,6 +407,7 @@ struct EpiGinit : EpiBase {
 // inner step, part A: H p = Q p + p/tau with p'Hp, g'p and the feasible
 // step; or, right after an expansion step, the fresh gradient g = H x - rhs
 struct EpiStepA : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 4;
     const double *p, *lv, *uv, *rhs;
     double *xt, *g, *hp;
@@ -522,6 +540,7 @@ struct EpiDir : EpiBase {
 // dual step (eq. dual_update) on the extrapolated point x_bar = 2 x_T - x
 // (eq. extrapolation), then the reflected Halpern average of y (Section 3.1)
 struct EpiDual : EpiBase {
+    static constexpr bool BULK = true;
     static constexpr int NR = 4;
     const double *xbar, *ya, *lc, *uc;
     double *y, *yt, *ytil;
@@ -916,19 +935,31 @@ int vec_grid(long long len)
 }
 
 template <class E>
+static void launch_spmv_main(const CsrDev& M, const E& e, double* partials, hipStream_t s)
+{
+    if constexpr (E::BULK) {
+        if (M.val32) {
+            k_spmv<E, true><<<M.nblk, TPB, 0, s>>>(M, e, partials);
+            return;
+        }
+    }
+    k_spmv<E, false><<<M.nblk, TPB, 0, s>>>(M, e, partials);
+}
+
+template <class E>
 static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s)
 {
     if (M.nparts > 1) {
         const int grid = vec_grid(M.rows);
         if (S.tev) (void)hipEventRecord(S.tev[0], s);
-        k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials);
+        launch_spmv_main(M, e, S.partials, s);
         k_rows<E><<<grid, TPB, 0, s>>>(M, e, S.partials);
         if (S.tev) (void)hipEventRecord(S.tev[1], s);
         if (E::NR > 0) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, S.partials);
         return hipGetLastError();
     }
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
-    k_spmv<E><<<M.nblk, TPB, 0, s>>>(M, e, S.partials);
+    launch_spmv_main(M, e, S.partials, s);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
     if (E::NR > 0 || M.nlr > 0) k_spmv_fin<E><<<1, FIN_T, 0, s>>>(M, e, S.partials);
     return hipGetLastError();
@@ -1126,6 +1157,18 @@ hipError_t launch_spmv_plain(const DevState& S, const CsrDev& M, const double* x
     e.ctrl = S.ctrl;
     e.x = x; e.y = y;
     return run_spmv(S, M, e, s);
+}
+
+__global__ __launch_bounds__(TPB) void k_to_f32(long long len, const double* src, float* dst)
+{
+    const long long stride = (long long)gridDim.x * TPB;
+    for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < len; i += stride) dst[i] = (float)src[i];
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, long long len, hipStream_t s)
+{
+    if (len > 0) k_to_f32<<<vec_grid(len), TPB, 0, s>>>(len, src, dst);
+    return hipGetLastError();
 }
 
 hipError_t launch_dot(const DevState& S, const double* a, const double* b, int len, hipStream_t s)

@@ -45,6 +45,7 @@ struct CsrDev {
     int* rowptr = nullptr;     // nparts x (rows + 1), absolute offsets
     int* col = nullptr;
     double* val = nullptr;
+    float* val32 = nullptr;    // FP32 copy of val (mixed precision), same layout
     BlkDesc* blk = nullptr;
     int nblk = 0;
     double* seg_part = nullptr;
@@ -177,6 +178,9 @@ struct BatchDev {
     const double* tval = nullptr;
     const int *qrp = nullptr, *qcol = nullptr;  // Q (block-diagonal, global indices)
     const double* qval = nullptr;
+    // FP32 copies of the values for the bulk products of a mixed-precision
+    // solve (all NULL in FP64)
+    const float *aval32 = nullptr, *tval32 = nullptr, *qval32 = nullptr;
     const double *qd = nullptr, *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
     // per instance
     const double *eta = nullptr, *omega0 = nullptr, *cmax = nullptr, *bscale = nullptr, *gammaq = nullptr;
@@ -200,5 +204,7 @@ hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* co
                              double tol, long long max_iter, double* v, double* w, double* u,
                              double* out, hipStream_t s);
 hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s);
+// dst[i] = (float)src[i]
+hipError_t launch_to_f32(const double* src, float* dst, long long len, hipStream_t s);
 
 }  // namespace pdhcg
