@@ -248,6 +248,72 @@ int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds);
 
 void qp_batch_destroy(qp_batch* bt);
 
+/* ---- request server: continuous batching ---------------------------------
+ *
+ * A server takes QPs of any size as they arrive and solves them on one GPU:
+ * requests with n + m <= batch_max_dim are gathered into batched launches
+ * (one workgroup per instance, as qp_batch_solve), the others are solved on
+ * the single-problem path by worker threads, each on its own stream.  Up to
+ * `batch_lanes` batched launches and `single_workers` single solves are in
+ * flight at once; a request is admitted when a lane or worker is free and
+ * the device bytes of everything in flight plus its own (its CSR data and
+ * solver state) stay within `device_budget`.  Requests that arrive while
+ * others run join the next launch of a free lane, so their work overlaps on
+ * the device with the launches already running.  Every solve keeps its
+ * iterates, Halpern anchor, restart and weight state on the device until it
+ * ends.  A request's result does not depend on the other requests it shares
+ * a launch with.  Thread-safe: any thread may submit, wait and fetch. */
+typedef struct qp_server qp_server;
+
+typedef struct {
+    int64_t device_budget;    /* bytes of device memory for requests in flight; 8 GiB */
+    int64_t batch_max_dim;    /* n + m at or below which a request joins a batch; 20000 */
+    int32_t batch_lanes;      /* batched launches in flight; 4 */
+    int32_t single_workers;   /* single-path solves in flight; 4 */
+    int32_t max_batch;        /* instances per batched launch; 1024 */
+    int32_t reserved;
+    double batch_linger_us;   /* a free lane waits up to this long (from the oldest waiting
+                                 request's arrival) for more requests before launching; 200 */
+} qp_server_config;
+
+/* Host times of one request, seconds since the server was created. */
+typedef struct {
+    double submitted, started, finished;
+    int32_t route;            /* 0: batched launch, 1: single-problem path */
+    int32_t batch_size;       /* instances of its launch (1 on the single path) */
+} qp_request_times;
+
+qp_server_config qp_server_config_default(void);
+
+/* Start a server (params as qp_solve_ex, NULL = defaults; cfg NULL =
+ * defaults).  Returns 0 and *out, or a negative error code. */
+int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_server** out);
+
+/* Submit one QP (arguments, validation and copying as qp_create; nothing is
+ * allocated on the device here).  Returns the request id (>= 0) or a
+ * negative error code; a request larger than device_budget is rejected with
+ * QP_ERR_INVALID_ARG. */
+int64_t qp_server_submit(qp_server* s, int64_t n, int64_t m,
+                         const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
+                         const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+                         const double* c, const double* b, const char* sense,
+                         const double* lb, const double* ub);
+
+/* Wait up to timeout_s seconds (< 0: no limit) for request `id`.  Returns
+ * its status (> 0) once solved, QP_NOT_SOLVED (0) on time-out, or a
+ * negative error code (unknown id, or the error its solve ended with). */
+int qp_server_wait(qp_server* s, int64_t id, double timeout_s);
+
+/* Result of a finished request, with the conventions of qp_result (host
+ * buffers of n and m entries, any pointer may be NULL), and its times.
+ * Releases the request: its id is unknown afterwards.  Returns its status
+ * or a negative error code (QP_ERR_STATE while it is not finished). */
+int qp_server_result(qp_server* s, int64_t id, double* x, double* y, qp_info* info,
+                     qp_request_times* times);
+
+/* Finish the requests in flight, drop the waiting ones and stop. */
+void qp_server_destroy(qp_server* s);
+
 /* ---- host-only diagnostics (no device call) --------------------------- */
 
 /* The SpMV work schedule the library builds for a CSR with `rows` rows and

@@ -67,6 +67,20 @@ class QPInfo(C.Structure):
         return d
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("device_budget", _i64), ("batch_max_dim", _i64), ("batch_lanes", C.c_int32),
+                ("single_workers", C.c_int32), ("max_batch", C.c_int32), ("reserved", C.c_int32),
+                ("batch_linger_us", C.c_double)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("submitted", C.c_double), ("started", C.c_double), ("finished", C.c_double),
+                ("route", C.c_int32), ("batch_size", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class QPError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (code {code})")
@@ -111,6 +125,16 @@ def lib():
         L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
+        L.qp_server_config_default.restype = ServerConfig
+        L.qp_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(QPParams), C.POINTER(C.c_void_p)]
+        L.qp_server_submit.argtypes = [C.c_void_p, _i64, _i64, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp,
+                                       C.c_char_p, _dp, _dp]
+        L.qp_server_submit.restype = _i64
+        L.qp_server_wait.argtypes = [C.c_void_p, _i64, C.c_double]
+        L.qp_server_result.argtypes = [C.c_void_p, _i64, _dp, _dp, C.POINTER(QPInfo),
+                                       C.POINTER(RequestTimes)]
+        L.qp_server_destroy.argtypes = [C.c_void_p]
+        L.qp_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -366,6 +390,88 @@ class BatchSolver:
 
     def close(self):
         qp_batch_destroy(self.h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- request server ---------------------------------------------------------------
+
+def qp_server_config_default(**overrides) -> ServerConfig:
+    c = lib().qp_server_config_default()
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def qp_server_create(cfg: ServerConfig | None = None, params: QPParams | None = None):
+    h = C.c_void_p()
+    _check(lib().qp_server_create(None if cfg is None else C.byref(cfg),
+                                  None if params is None else C.byref(params), C.byref(h)))
+    return h
+
+
+def qp_server_submit(h, n, m, Q, A, c, b, sense: bytes, lb=None, ub=None) -> int:
+    qp_, qj_, qv_, keepq = _csr(Q)
+    ap_, aj_, av_, keepa = _csr(A) if A is not None else (None, None, None, ())
+    c, b, lb, ub = _f64(c), _f64(b), _f64(lb), _f64(ub)
+    return _check(lib().qp_server_submit(h, n, m, qp_, qj_, qv_, ap_, aj_, av_, _d(c), _d(b), sense,
+                                         _d(lb), _d(ub)))
+
+
+def qp_server_wait(h, rid, timeout=-1.0) -> int:
+    return _check(lib().qp_server_wait(h, rid, timeout))
+
+
+def qp_server_result(h, rid, n, m):
+    """(status, x, y, info dict, times dict) of a finished request (releases it)."""
+    x = np.zeros(n)
+    y = np.zeros(max(m, 1))
+    info = QPInfo()
+    times = RequestTimes()
+    st = _check(lib().qp_server_result(h, rid, _d(x), _d(y), C.byref(info), C.byref(times)))
+    return st, x, y[:m], info.as_dict(), times.as_dict()
+
+
+def qp_server_destroy(h):
+    if h is not None and h.value:
+        lib().qp_server_destroy(h)
+        h.value = None
+
+
+class Server:
+    """Request server: submit(qp) -> id, wait(id), result(id) -> (Result, times)."""
+
+    def __init__(self, params: QPParams | None = None, **cfg):
+        self.h = qp_server_create(qp_server_config_default(**cfg), params)
+        self.shapes = {}
+
+    def submit(self, qp) -> int:
+        rid = qp_server_submit(self.h, qp.n, qp.m, qp.Q, qp.A, qp.c, qp.b, qp.sense, qp.lb, qp.ub)
+        self.shapes[rid] = (qp.n, qp.m)
+        return rid
+
+    def wait(self, rid, timeout=-1.0) -> int:
+        return qp_server_wait(self.h, rid, timeout)
+
+    def result(self, rid):
+        n, m = self.shapes.pop(rid)
+        st, x, y, info, times = qp_server_result(self.h, rid, n, m)
+        return Result(st, x, y, info), times
+
+    def close(self):
+        qp_server_destroy(self.h)
 
     def __enter__(self):
         return self

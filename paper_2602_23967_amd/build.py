@@ -1,4 +1,4 @@
-"""Build step of the gfx950 library: compiles csrc/*.hip and csrc/host.cpp
+"""Build step of the gfx950 library: compiles csrc/*.hip, csrc/host.cpp and csrc/serve.cpp
 with hipcc into libpdhcg_hip.so inside this package directory."""
 
 from __future__ import annotations
@@ -9,7 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdhcg_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "host.cpp", "serve.cpp")]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed FP32 instructions anywhere (hipcc's host pass warns about

@@ -274,12 +274,27 @@ namespace {
             return fail(QP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
+// A copy ordered on `s` that has completed when the call returns.  Every
+// copy of the library goes through a stream of its own handle (created
+// non-blocking), never the null stream, so one handle's copies do not wait
+// for the work of other handles in flight on the device.
+hipError_t copy_wait(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// Device memory comes from the stream-ordered allocator on the handle's own
+// stream (and goes back the same way), so creating and destroying handles
+// does not synchronise the device.
 template <class T>
 int dalloc(qp_handle* h, T** p, size_t count)
 {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&q, bytes);
+    hipError_t e = hipMallocAsync(&q, bytes, h->own);
     if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     h->dev_allocs.push_back(q);
     *p = static_cast<T*>(q);
@@ -313,7 +328,7 @@ int upload(qp_handle* h, T** p, const T* src, size_t count)
 {
     int rc = dalloc(h, p, count);
     if (rc) return rc;
-    if (count) HIPCHK(hipMemcpy(*p, src, count * sizeof(T), hipMemcpyHostToDevice));
+    if (count) HIPCHK(copy_wait(*p, src, count * sizeof(T), hipMemcpyHostToDevice, h->own));
     return 0;
 }
 
@@ -444,7 +459,8 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
         qp_destroy(h);
         return code;
     };
-    if (hipStreamCreate(&h->own) != hipSuccess) return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    if (hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
     h->stream = h->own;
     if (hipHostMalloc((void**)&h->hstat, 4 * sizeof(unsigned long long),
                       hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
@@ -753,7 +769,10 @@ void qp_destroy(qp_handle* h)
 {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    for (void* p : h->dev_allocs) (void)hipFree(p);
+    if (h->own) {
+        for (void* p : h->dev_allocs) (void)hipFreeAsync(p, h->own);
+        (void)hipStreamSynchronize(h->own);
+    }
     for (EventPair& e : h->ev_pool) {
         (void)hipEventDestroy(e.ev[0]);
         (void)hipEventDestroy(e.ev[1]);
@@ -815,7 +834,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                 }
                 HIPCHK(hipStreamSynchronize(s));
                 int st = 0;
-                HIPCHK(hipMemcpy(&st, &S.ctrl->status, sizeof(int), hipMemcpyDeviceToHost));
+                HIPCHK(copy_wait(&st, &S.ctrl->status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
                 if (st != 0) {
                     status = st;
                     break;
@@ -857,7 +876,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     const double t1 = now_s();
 
     Ctrl r;
-    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    HIPCHK(copy_wait(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     qp_info& I = h->info;
     std::memset(&I, 0, sizeof(I));
     I.status = status;
@@ -900,21 +919,21 @@ int qp_result(const qp_handle* h, double* x, double* y, qp_info* info)
     if (!h->solved) return fail(QP_ERR_STATE, "no solve has run on this handle");
     const DevState& S = h->S;
     Ctrl r;
-    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    HIPCHK(copy_wait(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     if (x) {
         if (h->status == QP_DUAL_INFEASIBLE) {
-            HIPCHK(hipMemcpy(x, S.dx, sizeof(double) * h->n, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(x, S.dx, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
             for (int64_t i = 0; i < h->n; ++i) x[i] /= r.d_max;
         } else {
-            HIPCHK(hipMemcpy(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
         }
     }
     if (y && h->m > 0) {
         if (h->status == QP_PRIMAL_INFEASIBLE) {
-            HIPCHK(hipMemcpy(y, S.ytil, sizeof(double) * h->m, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(y, S.ytil, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->stream));
             for (int64_t i = 0; i < h->m; ++i) y[i] /= r.ytil_max;
         } else {
-            HIPCHK(hipMemcpy(y, S.yt, sizeof(double) * h->m, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(y, S.yt, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->stream));
         }
     }
     if (info) *info = h->info;
@@ -970,7 +989,7 @@ int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double
     HIPCHK(hipMemcpyAsync(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     Ctrl r;
-    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    HIPCHK(copy_wait(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     if (iters) *iters = r.inner_it;
     if (res) *res = r.res;
     return 0;
@@ -987,7 +1006,7 @@ int qp_kkt(qp_handle* h, const double* x, const double* y, double* out)
     HIPCHK(launch_check(S, x, y ? y : S.y, 0, 0, s));
     HIPCHK(hipStreamSynchronize(s));
     Ctrl r;
-    HIPCHK(hipMemcpy(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    HIPCHK(copy_wait(&r, S.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
     out[0] = r.r_primal; out[1] = r.r_dual; out[2] = r.r_gap;
     out[3] = r.pobj; out[4] = r.dobj; out[5] = r.natural; out[6] = r.pviol;
     return 0;
@@ -1004,6 +1023,7 @@ struct qp_batch {
     std::vector<int64_t> voff, roff;
     BatchDev B;
     hipStream_t stream = nullptr;
+    bool own_stream = true;        // false: a stream lent by the caller (not destroyed)
     hipEvent_t done = nullptr;
     double t_launch = 0.0;
     int64_t nnz_a = 0, nnz_q = 0;
@@ -1022,7 +1042,7 @@ int balloc(qp_batch* bt, T** p, size_t count)
 {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&q, bytes);
+    hipError_t e = hipMallocAsync(&q, bytes, bt->stream);
     if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     bt->allocs.push_back(q);
     *p = static_cast<T*>(q);
@@ -1035,7 +1055,7 @@ int bupload(qp_batch* bt, const T** p, const T* src, size_t count)
     T* q = nullptr;
     int rc = balloc(bt, &q, count);
     if (rc) return rc;
-    if (count) HIPCHK(hipMemcpy(q, src, count * sizeof(T), hipMemcpyHostToDevice));
+    if (count) HIPCHK(copy_wait(q, src, count * sizeof(T), hipMemcpyHostToDevice, bt->stream));
     *p = q;
     return 0;
 }
@@ -1047,10 +1067,13 @@ extern "C" {
 void qp_batch_destroy(qp_batch* bt)
 {
     if (!bt) return;
-    if (bt->stream) (void)hipStreamSynchronize(bt->stream);
-    for (void* p : bt->allocs) (void)hipFree(p);
+    if (bt->stream) {
+        (void)hipStreamSynchronize(bt->stream);
+        for (void* p : bt->allocs) (void)hipFreeAsync(p, bt->stream);
+        (void)hipStreamSynchronize(bt->stream);
+    }
     if (bt->done) (void)hipEventDestroy(bt->done);
-    if (bt->stream) (void)hipStreamDestroy(bt->stream);
+    if (bt->stream && bt->own_stream) (void)hipStreamDestroy(bt->stream);
     delete bt;
 }
 
@@ -1059,6 +1082,20 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
                     const int64_t* Ap, const int32_t* Aj, const double* Av,
                     const double* c, const double* b, const char* sense,
                     const double* lb, const double* ub, qp_batch** out)
+{
+    return pdhcg::batch_create(nullptr, count, var_off, row_off, Qp, Qj, Qv, Ap, Aj, Av, c, b, sense, lb,
+                               ub, out);
+}
+
+}  // extern "C"
+
+namespace pdhcg {
+
+int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const int64_t* row_off,
+                 const int64_t* Qp, const int32_t* Qj, const double* Qv,
+                 const int64_t* Ap, const int32_t* Aj, const double* Av,
+                 const double* c, const double* b, const char* sense,
+                 const double* lb, const double* ub, qp_batch** out)
 {
     const double t0 = now_s();
     if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
@@ -1130,7 +1167,13 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     bt->m = m;
     bt->voff.assign(var_off, var_off + count + 1);
     bt->roff.assign(row_off, row_off + count + 1);
-    if (hipStreamCreate(&bt->stream) != hipSuccess || hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
+    if (lane) {
+        bt->stream = lane;
+        bt->own_stream = false;
+    } else if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) {
+        return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    }
+    if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
     BatchDev& B = bt->B;
     B.count = (int)count;
@@ -1176,7 +1219,7 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
         hipStreamSynchronize(bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
     bt->norm_A.resize(count);
-    if (hipMemcpy(bt->norm_A.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
+    if (copy_wait(bt->norm_A.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost, bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemcpy failed"));
     // ||Q_b||_2 for the instances with a non-diagonal Q (Q symmetric: Q' = Q)
     std::vector<double> normq_raw(count, 0.0);
@@ -1188,7 +1231,7 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
             launch_batch_norm(B, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
                               dp.power_tol, dp.power_max_iter, B.x, B.xa, B.xt, dnorm, bt->stream) != hipSuccess ||
             hipStreamSynchronize(bt->stream) != hipSuccess ||
-            hipMemcpy(normq_raw.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost) != hipSuccess)
+            copy_wait(normq_raw.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost, bt->stream) != hipSuccess)
             return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
     }
     std::vector<double> eta(count), om0(count), cmax(count), bsc(count), gq(count), nq(count);
@@ -1231,10 +1274,6 @@ int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_of
     g_err.clear();
     return 0;
 }
-
-}  // extern "C"
-
-namespace pdhcg {
 
 int batch_launch(qp_batch* bt, const qp_params* params)
 {
@@ -1280,6 +1319,58 @@ int batch_poll(qp_batch* bt)
     return fail(QP_ERR_DEVICE, std::string("batch solve failed: ") + hipGetErrorString(q));
 }
 
+void batch_info(const qp_batch* bt, int64_t i, qp_info* info)
+{
+    const BatchOut& o = bt->out[i];
+    std::memset(info, 0, sizeof(*info));
+    info->status = o.status;
+    info->precision = bt->B.aval32 ? QP_PRECISION_MIXED : QP_PRECISION_FP64;
+    info->iterations = o.iterations;
+    info->restarts = o.restarts;
+    info->inner_iterations = o.inner_iterations;
+    info->r_primal = o.r_primal;
+    info->r_dual = o.r_dual;
+    info->r_gap = o.r_gap;
+    info->primal_obj = o.pobj;
+    info->dual_obj = o.dobj;
+    info->omega = o.omega;
+    info->norm_A = bt->norm_A[i];
+    info->solve_seconds = bt->solve_seconds;
+    info->setup_seconds = bt->setup_seconds;
+}
+
+int batch_results_all(qp_batch* bt, std::vector<double>& x, std::vector<double>& y)
+{
+    if (!bt->solved) return fail(QP_ERR_STATE, "no solve has run on this batch");
+    bool pinf = false, dinf = false;
+    for (const BatchOut& o : bt->out) {
+        pinf |= o.status == QP_PRIMAL_INFEASIBLE;
+        dinf |= o.status == QP_DUAL_INFEASIBLE;
+    }
+    x.resize(bt->n);
+    y.resize(bt->m);
+    std::vector<double> d, yl;
+    HIPCHK(hipMemcpyAsync(x.data(), bt->B.xt, sizeof(double) * bt->n, hipMemcpyDeviceToHost, bt->stream));
+    if (bt->m) HIPCHK(hipMemcpyAsync(y.data(), bt->B.yt, sizeof(double) * bt->m, hipMemcpyDeviceToHost, bt->stream));
+    if (dinf) {
+        d.resize(bt->n);
+        HIPCHK(hipMemcpyAsync(d.data(), bt->B.d, sizeof(double) * bt->n, hipMemcpyDeviceToHost, bt->stream));
+    }
+    if (pinf && bt->m) {
+        yl.resize(bt->m);
+        HIPCHK(hipMemcpyAsync(yl.data(), bt->B.ytil, sizeof(double) * bt->m, hipMemcpyDeviceToHost, bt->stream));
+    }
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    for (int64_t i = 0; i < bt->count; ++i) {
+        const BatchOut& o = bt->out[i];
+        if (o.status == QP_DUAL_INFEASIBLE)
+            for (int64_t k = bt->voff[i]; k < bt->voff[i + 1]; ++k) x[k] = d[k] / o.d_max;
+        if (o.status == QP_PRIMAL_INFEASIBLE)
+            for (int64_t k = bt->roff[i]; k < bt->roff[i + 1]; ++k) y[k] = yl[k] / o.ytil_max;
+    }
+    return 0;
+}
+
 // waits for the launched solve and fetches the per-instance outcomes;
 // returns the number of OPTIMAL instances
 int batch_finish(qp_batch* bt)
@@ -1287,7 +1378,7 @@ int batch_finish(qp_batch* bt)
     HIPCHK(hipEventSynchronize(bt->done));
     bt->solve_seconds = now_s() - bt->t_launch;
     bt->out.resize(bt->count);
-    HIPCHK(hipMemcpy(bt->out.data(), bt->B.out, sizeof(BatchOut) * bt->count, hipMemcpyDeviceToHost));
+    HIPCHK(copy_wait(bt->out.data(), bt->B.out, sizeof(BatchOut) * bt->count, hipMemcpyDeviceToHost, bt->stream));
     bt->solved = 1;
     int opt = 0;
     for (const BatchOut& o : bt->out) opt += o.status == QP_OPTIMAL;
@@ -1315,36 +1406,21 @@ int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info
     const int64_t v0 = bt->voff[i], n = bt->voff[i + 1] - v0, r0 = bt->roff[i], m = bt->roff[i + 1] - r0;
     if (x) {
         if (o.status == QP_DUAL_INFEASIBLE) {
-            HIPCHK(hipMemcpy(x, bt->B.d + v0, sizeof(double) * n, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(x, bt->B.d + v0, sizeof(double) * n, hipMemcpyDeviceToHost, bt->stream));
             for (int64_t k = 0; k < n; ++k) x[k] /= o.d_max;
         } else {
-            HIPCHK(hipMemcpy(x, bt->B.xt + v0, sizeof(double) * n, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(x, bt->B.xt + v0, sizeof(double) * n, hipMemcpyDeviceToHost, bt->stream));
         }
     }
     if (y && m > 0) {
         if (o.status == QP_PRIMAL_INFEASIBLE) {
-            HIPCHK(hipMemcpy(y, bt->B.ytil + r0, sizeof(double) * m, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(y, bt->B.ytil + r0, sizeof(double) * m, hipMemcpyDeviceToHost, bt->stream));
             for (int64_t k = 0; k < m; ++k) y[k] /= o.ytil_max;
         } else {
-            HIPCHK(hipMemcpy(y, bt->B.yt + r0, sizeof(double) * m, hipMemcpyDeviceToHost));
+            HIPCHK(copy_wait(y, bt->B.yt + r0, sizeof(double) * m, hipMemcpyDeviceToHost, bt->stream));
         }
     }
-    if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->status = o.status;
-        info->iterations = o.iterations;
-        info->restarts = o.restarts;
-        info->inner_iterations = o.inner_iterations;
-        info->r_primal = o.r_primal;
-        info->r_dual = o.r_dual;
-        info->r_gap = o.r_gap;
-        info->primal_obj = o.pobj;
-        info->dual_obj = o.dobj;
-        info->omega = o.omega;
-        info->norm_A = bt->norm_A[i];
-        info->solve_seconds = bt->solve_seconds;
-        info->setup_seconds = bt->setup_seconds;
-    }
+    if (info) pdhcg::batch_info(bt, i, info);
     return o.status;
 }
 

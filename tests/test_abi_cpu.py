@@ -179,3 +179,26 @@ def test_batch_validation_errors():
         assert e.code == P.ERR_DEVICE                          # no GPU here
     else:
         P.qp_batch_destroy(h)
+
+
+def test_server_config_and_validation():
+    c = P.qp_server_config_default()
+    assert c.batch_lanes >= 1 and c.single_workers >= 1 and c.max_batch >= 1 and c.device_budget > 0
+    import ctypes as C
+    L = P.lib()
+    h = C.c_void_p()
+    bad = P.qp_server_config_default(batch_lanes=0, single_workers=0)
+    assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
+    bad = P.qp_server_config_default(max_batch=0)
+    assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
+    badp = P.qp_params_default(precision=3)
+    assert L.qp_server_create(None, C.byref(badp), C.byref(h)) == P.ERR_INVALID_ARG
+    assert L.qp_server_submit(None, 1, 0, None, None, None, None, None, None, None, None, None,
+                              None, None) == P.ERR_INVALID_ARG
+    assert L.qp_server_wait(None, 0, 0.0) == P.ERR_INVALID_ARG
+    L.qp_server_destroy(None)
+    rc = L.qp_server_create(None, None, C.byref(h))
+    if rc == 0:                                   # a GPU is present
+        L.qp_server_destroy(h)
+    else:
+        assert rc == P.ERR_DEVICE
