@@ -253,6 +253,88 @@ def main_portfolio(args, torch, P, I):
     print(json.dumps(out), flush=True)
 
 
+def main_serve(args, torch, P, I):
+    """A Poisson stream of mixed requests through the request server."""
+    import threading
+
+    t = time.perf_counter()
+    arrivals, qs = I.served_stream(args.requests, rate=args.rate)
+    kinds = [q.name.split("_")[0].rstrip("0123456789") for q in qs]
+    log(f"generated {len(qs)} requests in {time.perf_counter() - t:.1f}s: "
+        + ", ".join(f"{k} {kinds.count(k)}" for k in sorted(set(kinds))))
+    mixed = args.precision == "mixed"
+    params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter,
+                                 precision=P.PRECISION_MIXED if mixed else P.PRECISION_FP64)
+    cfg = dict(batch_lanes=args.lanes, single_workers=args.workers, batch_max_dim=args.batch_max_dim,
+               batch_linger_us=args.linger_us)
+    with P.Server(params, **cfg) as srv:
+        for q in (I.mpc(0), I.random_small(0, n=2000), I.portfolio(0, n_assets=10000, k_factors=50)):
+            srv.wait(srv.submit(q))                              # warm-up (not timed)
+        ids = [None] * len(qs)
+        t0 = time.perf_counter()
+
+        def feed():
+            for i, q in enumerate(qs):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[i] = srv.submit(q)
+
+        th = threading.Thread(target=feed)
+        th.start()
+        th.join()
+        res = []
+        for i, rid in enumerate(ids):
+            srv.wait(rid)
+            res.append(srv.result(rid))
+        elapsed = time.perf_counter() - t0
+    lat = np.array([tm["finished"] - tm["submitted"] for _, tm in res])
+    first = min(tm["submitted"] for _, tm in res)
+    last = max(tm["finished"] for _, tm in res)
+    ok = []
+    for q, (g, _) in zip(qs, res):
+        bad = q.name.endswith("_infeasible")
+        kkt = max(g.info["r_primal"], g.info["r_dual"], g.info["r_gap"])
+        ok.append(g.status == P.PRIMAL_INFEASIBLE if bad else (g.status == P.OPTIMAL and kkt <= args.tol))
+    per_kind = {}
+    for k in sorted(set(kinds)):
+        sel = np.array([kk == k for kk in kinds])
+        per_kind[k] = {"count": int(sel.sum()), "p50_s": float(np.percentile(lat[sel], 50)),
+                       "p99_s": float(np.percentile(lat[sel], 99)),
+                       "route": sorted({tm["route"] for (_, tm), s_ in zip(res, sel) if s_})}
+    # the plain FP64 form, one solve at a time, on a sample of the same stream
+    one, n_one = 0.0, 0
+    p64 = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
+    ta = time.perf_counter()
+    for q in qs:
+        if time.perf_counter() - ta > args.one_at_a_time_s:
+            break
+        a = time.perf_counter()
+        with P.Solver(q) as s1:
+            s1.solve(p64)
+        one += time.perf_counter() - a
+        n_one += 1
+    out = {
+        "metric": METRIC,
+        "value": len(qs) / (last - first),
+        "unit": "QPs solved/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * elapsed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 products + f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"served stream: {len(qs)} requests, Poisson arrivals at {args.rate:g}/s, "
+                               f"60% MPC / 30% random QP n~U(1e3,5e4) / 10% portfolio n~U(1e4,1e5), "
+                               f"2% infeasible, tol {args.tol:g}", **cfg},
+        "solved": int(np.sum(ok)), "requests": len(qs),
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "per_kind": per_kind},
+        "roofline": None,
+        "one_at_a_time": {"value": n_one / one if one else None, "unit": "QPs solved/s",
+                          "sample": f"first {n_one} requests of the stream, qp_create + qp_solve each, FP64"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,7 +346,16 @@ def main():
     ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
     ap.add_argument("--max-iter", type=int, default=100000,
                     help="outer iteration cap (lower only for short profiling runs)")
-    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch", "portfolio"], default="large_sparse")
+    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch", "portfolio", "serve"],
+                    default="large_sparse")
+    ap.add_argument("--requests", type=int, default=1000, help="requests of the served stream")
+    ap.add_argument("--rate", type=float, default=2000.0, help="arrivals per second of the served stream")
+    ap.add_argument("--lanes", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--batch-max-dim", type=int, default=20000)
+    ap.add_argument("--linger-us", type=float, default=200.0)
+    ap.add_argument("--one-at-a-time-s", type=float, default=20.0,
+                    help="seconds spent solving the served stream one request at a time (FP64)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="arithmetic of the portfolio and batched workloads (default: mixed for them; "
                          "the large sparse workload is FP64)")
@@ -306,6 +397,10 @@ def main():
         if args.precision is None:
             args.precision = "mixed"
         return main_portfolio(args, torch, P, I)
+    if args.workload == "serve":
+        if args.precision is None:
+            args.precision = "mixed"
+        return main_serve(args, torch, P, I)
 
     t = time.perf_counter()
     q = I.large_sparse(0, n=args.n)

@@ -158,6 +158,20 @@ int qp_create_ranged(int64_t n, int64_t m,
                      const double* c, const double* lc, const double* uc,
                      const double* lb, const double* ub, qp_handle** out);
 
+/* Same as qp_create with a structured quadratic term Q = P + R'R (Section
+ * 2.2, structured quadratic objective): P is sparse symmetric n x n CSR (may
+ * be NULL for P = 0) and R is k x n CSR (k >= 1, usually k << n).  R'R is
+ * never formed: every product with Q is a product with R (k rows) followed
+ * by one with the n x (n + k) matrix [P | R'] on [v; R v].  Validation as
+ * qp_create, plus R's CSR rules and n + k < 2^31.  qp_apply(QP_OP_Q) applies
+ * P + R'R. */
+int qp_create_factored(int64_t n, int64_t m,
+                       const int64_t* P_rowptr, const int32_t* P_col, const double* P_val,
+                       int64_t k, const int64_t* R_rowptr, const int32_t* R_col, const double* R_val,
+                       const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+                       const double* c, const double* b, const char* sense,
+                       const double* lb, const double* ub, qp_handle** out);
+
 /* Run every later call of this handle on `stream` (a hipStream_t; NULL
  * selects the handle's own stream).  The caller keeps ownership. */
 int qp_set_stream(qp_handle* h, void* stream);
@@ -224,8 +238,14 @@ int qp_norms(const qp_handle* h, double* norm_A, double* norm_Q);
  * status: the closed-form primal step when its block of Q is diagonal, the
  * boxed conjugate-gradient inner solve otherwise.  One workgroup solves one
  * instance at a time, so an instance's result does not depend on which other
- * instances share the launch.  Same ownership and error rules as qp_create. */
+ * instances share the launch.  Same ownership and error rules as qp_create;
+ * a row longer than QP_BATCH_MAX_ROW is QP_ERR_INVALID_ARG. */
 typedef struct qp_batch qp_batch;
+
+/* Longest row of A, of A' (column of A) and of Q an instance of a batch may
+ * have: the batched kernel sums each row with one thread.  Instances with
+ * longer rows belong on the single-problem path. */
+#define QP_BATCH_MAX_ROW 256
 
 int qp_batch_create(int64_t count, const int64_t* var_off, const int64_t* row_off,
                     const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
@@ -251,8 +271,9 @@ void qp_batch_destroy(qp_batch* bt);
 /* ---- request server: continuous batching ---------------------------------
  *
  * A server takes QPs of any size as they arrive and solves them on one GPU:
- * requests with n + m <= batch_max_dim are gathered into batched launches
- * (one workgroup per instance, as qp_batch_solve), the others are solved on
+ * requests with n + m <= batch_max_dim and no row of A, A' or Q longer than
+ * QP_BATCH_MAX_ROW nonzeros are gathered into batched launches (one workgroup per
+ * instance, as qp_batch_solve), the others are solved on
  * the single-problem path by worker threads, each on its own stream.  Up to
  * `batch_lanes` batched launches and `single_workers` single solves are in
  * flight at once; a request is admitted when a lane or worker is free and

@@ -103,6 +103,8 @@ def lib():
                                 _dp, _dp, C.POINTER(C.c_void_p)]
         L.qp_create_ranged.argtypes = [_i64, _i64, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp, _dp,
                                        _dp, _dp, C.POINTER(C.c_void_p)]
+        L.qp_create_factored.argtypes = [_i64, _i64, _lp, _ip, _dp, _i64, _lp, _ip, _dp, _lp, _ip, _dp,
+                                         _dp, _dp, C.c_char_p, _dp, _dp, C.POINTER(C.c_void_p)]
         L.qp_set_stream.argtypes = [C.c_void_p, C.c_void_p]
         L.qp_solve.argtypes = [C.c_void_p, C.c_double, _i64]
         L.qp_solve_ex.argtypes = [C.c_void_p, C.POINTER(QPParams)]
@@ -209,8 +211,22 @@ def qp_create_ranged(n, m, Q, A, c, lc, uc, lb=None, ub=None):
     return h
 
 
+def qp_create_factored(n, m, P, R, A, c, b, sense: bytes, lb=None, ub=None):
+    """Q = P + R'R from its factors (P may be None; R k x n)."""
+    pp_, pj_, pv_, keepp = _csr(P)
+    rp_, rj_, rv_, keepr = _csr(R)
+    ap_, aj_, av_, keepa = _csr(A) if A is not None else (None, None, None, ())
+    c, b, lb, ub = _f64(c), _f64(b), _f64(lb), _f64(ub)
+    h = C.c_void_p()
+    _check(lib().qp_create_factored(n, m, pp_, pj_, pv_, R.shape[0], rp_, rj_, rv_, ap_, aj_, av_,
+                                    _d(c), _d(b), sense, _d(lb), _d(ub), C.byref(h)))
+    return h
+
+
 def qp_create_from(qp):
-    """Handle for a paper_2602_23967_amd.instances.QP."""
+    """Handle for a paper_2602_23967_amd.instances.QP (factored when qp.R is set)."""
+    if getattr(qp, "R", None) is not None:
+        return qp_create_factored(qp.n, qp.m, qp.Q, qp.R, qp.A, qp.c, qp.b, qp.sense, qp.lb, qp.ub)
     return qp_create(qp.n, qp.m, qp.Q, qp.A, qp.c, qp.b, qp.sense, qp.lb, qp.ub)
 
 

@@ -262,7 +262,7 @@ struct qp_handle {
     int timing = 0;
     int64_t fam_launches[QP_NFAM] = {};
     // FP32 copies of the matrix values, made at the first mixed-precision solve
-    float *val32_A = nullptr, *val32_AT = nullptr, *val32_Q = nullptr;
+    float *val32_A = nullptr, *val32_AT = nullptr, *val32_Q = nullptr, *val32_R = nullptr;
 };
 
 namespace {
@@ -307,8 +307,8 @@ int set_precision(qp_handle* h, int precision)
 {
     DevState& S = h->S;
     if (precision == QP_PRECISION_MIXED) {
-        struct Item { CsrDev* M; float** keep; } items[3] = {{&S.A, &h->val32_A}, {&S.AT, &h->val32_AT},
-                                                            {&S.Q, &h->val32_Q}};
+        struct Item { CsrDev* M; float** keep; } items[4] = {{&S.A, &h->val32_A}, {&S.AT, &h->val32_AT},
+                                                            {&S.Q, &h->val32_Q}, {&S.R, &h->val32_R}};
         for (Item& it : items) {
             if (it.M->nnz == 0 || !it.M->val) continue;
             if (!*it.keep) {
@@ -318,7 +318,7 @@ int set_precision(qp_handle* h, int precision)
             it.M->val32 = *it.keep;
         }
     } else {
-        S.A.val32 = S.AT.val32 = S.Q.val32 = nullptr;
+        S.A.val32 = S.AT.val32 = S.Q.val32 = S.R.val32 = nullptr;
     }
     return 0;
 }
@@ -389,8 +389,10 @@ hipStream_t stream_of(const qp_handle* h) { return h->stream; }
 // power-iteration estimate of ||M||_2 through M'M (Mt = M' as a CSR),
 // the same sequence as the oracle: w = M v, sigma = ||w||, u = M' w,
 // v = u / ||u||, stop when sigma changes by <= tol * sigma
+// ||M||_2 by power iteration on M'M.  is_q: M is the (symmetric) Q operator,
+// applied as [P | R'] on [v; R v] when Q is factored.
 int power_norm(qp_handle* h, const CsrDev& M, const CsrDev& Mt, double tol, int64_t max_iter,
-               double* out)
+               double* out, bool is_q = false)
 {
     *out = 0.0;
     if (M.rows == 0 || M.cols == 0 || M.nnz == 0) return 0;
@@ -398,15 +400,18 @@ int power_norm(qp_handle* h, const CsrDev& M, const CsrDev& Mt, double tol, int6
     hipStream_t s = stream_of(h);
     double* v = S.v1;
     double* w = S.v2;
-    HIPCHK(launch_power_start(S, v, M.cols, s));
-    HIPCHK(launch_scale(S, v, M.cols, s));
+    const int cols = is_q ? S.n : M.cols;
+    HIPCHK(launch_power_start(S, v, cols, s));
+    HIPCHK(launch_scale(S, v, cols, s));
     double sig = 0.0, prev = 0.0;
     for (int64_t it = 1; it <= max_iter; ++it) {
+        if (is_q) HIPCHK(launch_tail(S, v, v + S.n, false, s));
         HIPCHK(launch_spmv_norm(S, M, v, w, s));
         HIPCHK(hipMemcpyAsync(&h->hcheck[1], &S.ctrl->pw_norm, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (is_q) HIPCHK(launch_tail(S, w, w + S.n, false, s));
         HIPCHK(launch_spmv_norm(S, Mt, w, v, s));
         HIPCHK(hipMemcpyAsync(&h->hcheck[2], &S.ctrl->pw_norm, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(launch_scale(S, v, M.cols, s));
+        HIPCHK(launch_scale(S, v, cols, s));
         HIPCHK(hipStreamSynchronize(s));
         double nu;
         std::memcpy(&sig, &h->hcheck[1], sizeof(double));
@@ -419,10 +424,13 @@ int power_norm(qp_handle* h, const CsrDev& M, const CsrDev& Mt, double tol, int6
     return 0;
 }
 
+// Q is either given as one CSR (k == 0) or as P (in Qp/Qj/Qv, may be NULL)
+// plus R'R with R k x n CSR.
 int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, const double* Qv,
                 const int64_t* Ap, const int32_t* Aj, const double* Av, const double* c,
                 const double* lc, const double* uc, const double* lb, const double* ub,
-                qp_handle** out)
+                qp_handle** out, int64_t k = 0, const int64_t* Rp = nullptr,
+                const int32_t* Rj = nullptr, const double* Rv = nullptr)
 {
     const double t0 = now_s();
     int rc;
@@ -442,6 +450,11 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if (Qp) {
         if ((rc = check_csr("Q", n, n, Qp, Qj, Qv))) return rc;
         if ((rc = check_symmetric(n, Qp, Qj, Qv))) return rc;
+    }
+    if (k < 0 || k >= INT32_MAX || n + k >= INT32_MAX) return fail(QP_ERR_INVALID_ARG, "bad factor rank k");
+    if (k > 0) {
+        if (!Rp) return fail(QP_ERR_INVALID_ARG, "R: row pointer is NULL");
+        if ((rc = check_csr("R", k, n, Rp, Rj, Rv))) return rc;
     }
 
     // ---- device setup -------------------------------------------------------
@@ -474,7 +487,27 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     // Q kind: none, diagonal (closed-form primal step) or general
     std::vector<double> qd(n, 0.0);
     h->qkind = 0;
-    if (Qp) {
+    // factored Q: the product matrix [P | R'] (n x (n + k)) and R
+    std::vector<int64_t> mp, rtp;
+    std::vector<int32_t> mj, rtj;
+    std::vector<double> mv, rtv;
+    if (k > 0) {
+        transpose(k, n, Rp, Rj, Rv, rtp, rtj, rtv);
+        mp.assign(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i)
+            mp[i + 1] = mp[i] + (Qp ? Qp[i + 1] - Qp[i] : 0) + (rtp[i + 1] - rtp[i]);
+        mj.resize(mp[n]);
+        mv.resize(mp[n]);
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t q = mp[i];
+            if (Qp)
+                for (int64_t e = Qp[i]; e < Qp[i + 1]; ++e) { mj[q] = Qj[e]; mv[q] = Qv[e]; ++q; }
+            for (int64_t e = rtp[i]; e < rtp[i + 1]; ++e) { mj[q] = (int32_t)(n + rtj[e]); mv[q] = rtv[e]; ++q; }
+        }
+        if (mp[n] >= INT32_MAX) return bail(fail(QP_ERR_INVALID_ARG, "too many nonzeros in [P | R']"));
+        h->qkind = 2;
+        S.k = (int)k;
+    } else if (Qp) {
         h->qkind = 1;
         for (int64_t i = 0; i < n && h->qkind == 1; ++i)
             for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k)
@@ -492,7 +525,12 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if ((rc = upload_csr(h, S.A, m, n, Ap, Aj, Av))) return bail(rc);
     if ((rc = upload_csr(h, S.AT, n, m, tp.data(), tj.data(), tv.data()))) return bail(rc);
     std::vector<int64_t> q_empty(n + 1, 0);
-    if ((rc = upload_csr(h, S.Q, n, n, Qp ? Qp : q_empty.data(), Qj, Qv))) return bail(rc);
+    if (k > 0) {
+        if ((rc = upload_csr(h, S.Q, n, n + k, mp.data(), mj.data(), mv.data()))) return bail(rc);
+        if ((rc = upload_csr(h, S.R, k, n, Rp, Rj, Rv))) return bail(rc);
+    } else {
+        if ((rc = upload_csr(h, S.Q, n, n, Qp ? Qp : q_empty.data(), Qj, Qv))) return bail(rc);
+    }
 
     std::vector<double> lcv(m), ucv(m);
     for (int64_t i = 0; i < m; ++i) { lcv[i] = lc[i]; ucv[i] = uc[i]; }
@@ -502,26 +540,29 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if ((rc = upload(h, &S.uv, uvv.data(), n))) return bail(rc);
     if ((rc = upload(h, &S.lc, lcv.data(), m))) return bail(rc);
     if ((rc = upload(h, &S.uc, ucv.data(), m))) return bail(rc);
-    double** nvecs[] = {&S.x, &S.xa, &S.xt, &S.rhs, &S.g, &S.p, &S.hp, &S.aty, &S.dx, &S.xbar};
+    double** nvecs[] = {&S.x, &S.xa, &S.rhs, &S.g, &S.hp, &S.aty, &S.xbar};
     for (double** pv : nvecs)
         if ((rc = dalloc(h, pv, n))) return bail(rc);
+    double** tvecs[] = {&S.xt, &S.p, &S.dx};   // operands of Q: room for R times them
+    for (double** pv : tvecs)
+        if ((rc = dalloc(h, pv, n + k))) return bail(rc);
     double** mvecs[] = {&S.y, &S.ya, &S.yt, &S.ytil};
     for (double** pv : mvecs)
         if ((rc = dalloc(h, pv, m))) return bail(rc);
-    const int64_t nm = std::max(n, m);
+    const int64_t nm = std::max(n, m) + k;
     if ((rc = dalloc(h, &S.v1, nm))) return bail(rc);
     if ((rc = dalloc(h, &S.v2, nm))) return bail(rc);
     if ((rc = dalloc(h, &S.ctrl, 1))) return bail(rc);
-    const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, VEC_GRID_MAX});   // partials slots
+    const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, S.R.nblk, VEC_GRID_MAX});   // partials slots
     if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8))) return bail(rc);
-    if (hipMemset(S.ctrl, 0, sizeof(Ctrl)) != hipSuccess)
+    if (hipMemsetAsync(S.ctrl, 0, sizeof(Ctrl), h->own) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemset failed"));
 
     // scalars of the problem
     qp_params d = qp_params_default();
     if ((rc = power_norm(h, S.A, S.AT, d.power_tol, d.power_max_iter, &h->norm_A))) return bail(rc);
     if (h->qkind == 2) {
-        if ((rc = power_norm(h, S.Q, S.Q, d.power_tol, d.power_max_iter, &h->norm_Q_raw))) return bail(rc);
+        if ((rc = power_norm(h, S.Q, S.Q, d.power_tol, d.power_max_iter, &h->norm_Q_raw, true))) return bail(rc);
         h->norm_Q = d.norm_safety * h->norm_Q_raw;
     } else {
         h->norm_Q = 0.0;
@@ -545,12 +586,21 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     }
     h->bscale_p = 1.0 + bl;
     h->gamma_q = 1.0;
-    if (Qp)
-        for (int64_t i = 0; i < n; ++i) {
-            double s = 0.0;
-            for (int64_t k = Qp[i]; k < Qp[i + 1]; ++k) s += std::fabs(Qv[k]);
-            h->gamma_q = std::max(h->gamma_q, s);
+    {
+        // row sums of |Q|; for a factored Q the bound |P| + |R|'|R| 1
+        std::vector<double> rs(n, 0.0);
+        if (Qp)
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t e = Qp[i]; e < Qp[i + 1]; ++e) rs[i] += std::fabs(Qv[e]);
+        if (k > 0) {
+            std::vector<double> r1(k, 0.0);
+            for (int64_t r = 0; r < k; ++r)
+                for (int64_t e = Rp[r]; e < Rp[r + 1]; ++e) r1[r] += std::fabs(Rv[e]);
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t e = rtp[i]; e < rtp[i + 1]; ++e) rs[i] += std::fabs(rtv[e]) * r1[rtj[e]];
         }
+        for (int64_t i = 0; i < n; ++i) h->gamma_q = std::max(h->gamma_q, rs[i]);
+    }
     h->has_unbounded_x = 0;
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(lvv[i]) || !std::isfinite(uvv[i])) h->has_unbounded_x = 1;
@@ -758,6 +808,33 @@ int qp_create_ranged(int64_t n, int64_t m, const int64_t* Q_rowptr, const int32_
                        u.data(), lb, ub, out);
 }
 
+int qp_create_factored(int64_t n, int64_t m, const int64_t* P_rowptr, const int32_t* P_col,
+                       const double* P_val, int64_t k, const int64_t* R_rowptr, const int32_t* R_col,
+                       const double* R_val, const int64_t* A_rowptr, const int32_t* A_col,
+                       const double* A_val, const double* c, const double* b, const char* sense,
+                       const double* lb, const double* ub, qp_handle** out)
+{
+    if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n >= INT32_MAX || m < 0 || m >= INT32_MAX)
+        return fail(QP_ERR_INVALID_ARG, "need 1 <= n < 2^31 and 0 <= m < 2^31");
+    if (k < 1) return fail(QP_ERR_INVALID_ARG, "need k >= 1 (use qp_create without factors)");
+    if (m > 0 && (!b || !sense)) return fail(QP_ERR_INVALID_ARG, "b or sense is NULL");
+    int rc = check_vec("b", m, b, false);
+    if (m > 0 && rc) return rc;
+    std::vector<double> lc(m), uc(m);
+    for (int64_t i = 0; i < m; ++i) {
+        switch (sense[i]) {
+        case 'E': lc[i] = b[i]; uc[i] = b[i]; break;
+        case 'G': lc[i] = b[i]; uc[i] = INFINITY; break;
+        case 'L': lc[i] = -INFINITY; uc[i] = b[i]; break;
+        default: return fail(QP_ERR_INVALID_ARG, "sense: unknown character at row " + std::to_string(i));
+        }
+    }
+    return create_impl(n, m, P_rowptr, P_col, P_val, A_rowptr, A_col, A_val, c, lc.data(), uc.data(), lb, ub,
+                       out, k, R_rowptr, R_col, R_val);
+}
+
 int qp_set_stream(qp_handle* h, void* stream)
 {
     if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
@@ -945,6 +1022,12 @@ int qp_apply(qp_handle* h, int op, const double* x, double* y)
     if (!h || !x || !y) return fail(QP_ERR_INVALID_ARG, "NULL argument");
     const CsrDev* M = op == QP_OP_Q ? &h->S.Q : op == QP_OP_A ? &h->S.A : op == QP_OP_AT ? &h->S.AT : nullptr;
     if (!M) return fail(QP_ERR_INVALID_ARG, "unknown operator");
+    if (op == QP_OP_Q && h->S.k > 0) {
+        // [P | R'] on [x; R x]
+        HIPCHK(hipMemcpyAsync(h->S.v1, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(launch_tail(h->S, h->S.v1, h->S.v1 + h->n, false, h->stream));
+        x = h->S.v1;
+    }
     HIPCHK(launch_spmv_plain(h->S, *M, x, y, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return 0;
@@ -1157,6 +1240,19 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
             for (int64_t k = Ap[r]; k < Ap[r + 1]; ++k)
                 if (Aj[k] < var_off[i] || Aj[k] >= var_off[i + 1])
                     return fail(QP_ERR_INVALID_ARG, "A is not block-diagonal at row " + std::to_string(r));
+    // the kernel sums each row with one thread; rows longer than
+    // QP_BATCH_MAX_ROW nonzeros (of A, A' or Q) are not accepted
+    {
+        std::vector<int64_t> colcnt(n, 0);
+        for (int64_t k = 0; k < Ap[m]; ++k) ++colcnt[Aj[k]];
+        for (int64_t r = 0; r < m; ++r)
+            if (Ap[r + 1] - Ap[r] > QP_BATCH_MAX_ROW)
+                return fail(QP_ERR_INVALID_ARG, "row " + std::to_string(r) + " of A is longer than QP_BATCH_MAX_ROW");
+        for (int64_t j = 0; j < n; ++j)
+            if (colcnt[j] > QP_BATCH_MAX_ROW || Qp[j + 1] - Qp[j] > QP_BATCH_MAX_ROW)
+                return fail(QP_ERR_INVALID_ARG,
+                            "column " + std::to_string(j) + " of A or row of Q is longer than QP_BATCH_MAX_ROW");
+    }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(QP_ERR_DEVICE, "no HIP device available");

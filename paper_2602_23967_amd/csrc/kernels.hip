@@ -99,8 +99,15 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
+#if PDHCG_NT
+            // matrix entries are used once per product: stream them past the
+            // caches so the gathered operand part stays resident in L2
+            cj[i] = q < cnt ? __builtin_nontemporal_load(M.col + d.k0 + q) : -1;
+            av[i] = q < cnt ? __builtin_nontemporal_load(val + d.k0 + q) : T(0);
+#else
             cj[i] = q < cnt ? M.col[d.k0 + q] : -1;
             av[i] = q < cnt ? val[d.k0 + q] : T(0);
+#endif
         }
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
@@ -634,6 +641,35 @@ struct EpiHalpX : EpiBase {
     }
 };
 
+// ---- Q = P + R'R given by its factors (Section 2.2) -------------------------
+// A product with Q is a product with the n x (n + k) matrix [P | R'] on the
+// operand [v; R v]: the k entries R v live right after the operand's n
+// entries.  These epilogues compute that tail.
+
+// tail = R v (Bulk: part of the iteration, FP32 in mixed precision)
+template <bool Bulk>
+struct EpiTail : EpiBase {
+    static constexpr bool BULK = Bulk;
+    static constexpr int NR = 0;
+    const double* v;
+    double* tail;
+    __device__ double xval(int j) const { return v[j]; }
+    __device__ void row(int r, double s, Acc<NR>) const { tail[r] = s; }
+};
+
+// the tail of the inner step's operand: R p, or R x right after an expansion
+struct EpiTailHp : EpiBase {
+    static constexpr bool BULK = true;
+    static constexpr int NR = 0;
+    const double *p, *xt;
+    double *ptail, *xtail;
+    int ng;
+    __device__ bool skip() const { return ctrl->done != 0; }
+    __device__ void init() { ng = ctrl->need_g; }
+    __device__ double xval(int j) const { return ng ? xt[j] : p[j]; }
+    __device__ void row(int r, double s, Acc<NR>) const { (ng ? xtail : ptail)[r] = s; }
+};
+
 // ---- check kernels (Sections 4 and 5) -------------------------------------
 
 // w = A' ytil: violation of A'ytil in R and p(-proj_R(A'ytil); l_v, u_v)
@@ -1012,8 +1048,27 @@ hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s)
     return run_spmv(S, S.AT, e, s);
 }
 
+hipError_t launch_tail(const DevState& S, const double* v, double* tail, bool bulk, hipStream_t s)
+{
+    if (S.R.rows == 0) return hipSuccess;
+    if (bulk) {
+        EpiTail<true> e{};
+        e.ctrl = S.ctrl;
+        e.v = v; e.tail = tail;
+        return run_spmv(S, S.R, e, s);
+    }
+    EpiTail<false> e{};
+    e.ctrl = S.ctrl;
+    e.v = v; e.tail = tail;
+    return run_spmv(S, S.R, e, s);
+}
+
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s)
 {
+    if (S.R.rows) {
+        hipError_t err = launch_tail(S, S.xt, S.xt + S.n, true, s);
+        if (err != hipSuccess) return err;
+    }
     EpiGinit e{};
     e.ctrl = S.ctrl;
     e.xt = S.xt; e.rhs = S.rhs; e.lv = S.lv; e.uv = S.uv; e.g = S.g;
@@ -1031,6 +1086,13 @@ hipError_t launch_dir(const DevState& S, hipStream_t s)
 
 hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s)
 {
+    if (S.R.rows) {
+        EpiTailHp t{};
+        t.ctrl = S.ctrl;
+        t.p = S.p; t.xt = S.xt; t.ptail = S.p + S.n; t.xtail = S.xt + S.n;
+        hipError_t err = run_spmv(S, S.R, t, s);
+        if (err != hipSuccess) return err;
+    }
     EpiStepA e{};
     e.ctrl = S.ctrl;
     e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
@@ -1092,6 +1154,7 @@ hipError_t launch_check(const DevState& S, const double* x, const double* y, int
         ep.ytil = S.ytil; ep.lv = S.lv; ep.uv = S.uv;
         if ((err = run_spmv(S, S.AT, ep, s)) != hipSuccess) return err;
         if (dinf) {
+            if ((err = launch_tail(S, S.dx, S.dx + S.n, false, s)) != hipSuccess) return err;
             EpiAd ea{};
             ea.ctrl = S.ctrl;
             ea.d = S.dx; ea.lc = S.lc; ea.uc = S.uc;
@@ -1110,6 +1173,17 @@ hipError_t launch_check(const DevState& S, const double* x, const double* y, int
     ex.ctrl = S.ctrl;
     ex.x = x; ex.y = y; ex.ya = full ? S.ya : nullptr; ex.lc = S.lc; ex.uc = S.uc;
     if ((err = run_spmv(S, S.A, ex, s)) != hipSuccess) return err;
+    if (S.R.rows) {
+        // the operand needs room for its tail: x_T has it, any other x is copied
+        double* xq = S.xt;
+        if (x != S.xt) {
+            xq = S.v1;
+            if ((err = hipMemcpyAsync(xq, x, sizeof(double) * S.n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+                return err;
+        }
+        if ((err = launch_tail(S, xq, xq + S.n, false, s)) != hipSuccess) return err;
+        x = xq;
+    }
     EpiQx eq{};
     eq.ctrl = S.ctrl;
     eq.x = x; eq.xa = full ? S.xa : nullptr; eq.c = S.c; eq.aty = S.aty; eq.lv = S.lv; eq.uv = S.uv;

@@ -21,6 +21,9 @@ constexpr int VEC_GRID_MAX = 2048;
 #define PDHCG_NPARTS 4
 #endif
 constexpr int NPARTS = PDHCG_NPARTS;
+#ifndef PDHCG_NT
+#define PDHCG_NT 0
+#endif
 constexpr int PART_MIN_COLS = 262144;
 constexpr int PART_ROWS_CAP = 1024;   // rows per block of a column part
 constexpr int FIN_T = 1024;     // threads of the one-block finishing kernels
@@ -102,6 +105,10 @@ struct Ctrl {
 struct DevState {
     int n = 0, m = 0;
     CsrDev Q, A, AT;
+    // Q = P + R'R given by its factors: Q holds [P | R'] (n x (n + k)), R is
+    // k x n, and x_T, p, dx, v1, v2 carry k extra entries for R times them
+    CsrDev R;
+    int k = 0;
     int qdiag = 0;                 // Q diagonal (closed-form primal step)
     double* qd = nullptr;          // diagonal of Q (n)
     double *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
@@ -123,6 +130,8 @@ hipError_t launch_init_start(const DevState& S, hipStream_t s);
 hipError_t launch_prox_diag(const DevState& S, hipStream_t s);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
+// tail = R v for a factored Q (no-op otherwise); bulk: FP32 in mixed precision
+hipError_t launch_tail(const DevState& S, const double* v, double* tail, bool bulk, hipStream_t s);
 // rhs and warm-start gradient of the next subproblem from the previous one's
 // gradient (no product with Q); starts the inner solve like launch_ginit
 hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s);

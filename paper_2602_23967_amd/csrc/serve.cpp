@@ -417,7 +417,19 @@ int64_t qp_server_submit(qp_server* s, int64_t n, int64_t m,
         r->b.assign(b, b + m);
         r->sense.assign(sense, sense + m);
     }
-    r->route = (s->cfg.batch_lanes > 0 && (n + m <= s->cfg.batch_max_dim || s->cfg.single_workers == 0)) ? 0 : 1;
+    // the batched kernel sums each row with one thread: a long row (a budget
+    // row over every asset, a dense column of A) would serialise its instance
+    int64_t longest = 0;
+    for (int64_t i = 0; i < m; ++i) longest = std::max(longest, Ap[i + 1] - Ap[i]);
+    if (Qp)
+        for (int64_t i = 0; i < n; ++i) longest = std::max(longest, Qp[i + 1] - Qp[i]);
+    {
+        std::vector<int64_t> colcnt(n, 0);
+        for (int64_t e = 0; e < Ap[m]; ++e) ++colcnt[Aj[e]];
+        for (int64_t i = 0; i < n; ++i) longest = std::max(longest, colcnt[i]);
+    }
+    const bool small = n + m <= s->cfg.batch_max_dim && longest <= QP_BATCH_MAX_ROW;
+    r->route = (s->cfg.batch_lanes > 0 && (small || s->cfg.single_workers == 0)) ? 0 : 1;
     r->bytes = footprint(*r, r->route);
     if (r->bytes > (size_t)s->cfg.device_budget) return fail(QP_ERR_INVALID_ARG, "request exceeds the device budget");
     r->t_submit = t_submit;

@@ -29,6 +29,8 @@ SEED_ROOT = 260223967
 FAM_RANDOM_SMALL = 0      # n=1000 random sparse QP (B^T B + 1e-2 I)
 FAM_LARGE_SPARSE = 1      # n=1e6 diagonally dominant sparse QP
 FAM_PORTFOLIO = 2         # factor-model portfolio, diagonal Q
+FAM_SERVED = 4            # request streams for the server (kinds, sizes, arrivals)
+FAM_FACTORED = 5          # QPs with Q = P + R'R given by its factors
 FAM_TINY = 10             # tiny QPs for brute-force pins
 FAM_LP = 11               # tiny LPs (Q = 0)
 FAM_EQ = 12               # equality-only, unboxed QPs (dense KKT pins)
@@ -50,6 +52,21 @@ class QP:
     ub: np.ndarray
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # Q = P + R'R given by its factors (Q then holds P, or None for P = 0)
+    R: sp.csr_matrix | None = None
+
+    def explicit_Q(self) -> sp.csr_matrix | None:
+        """Q written out (P + R'R formed; only for small instances)."""
+        if self.R is None:
+            return self.Q
+        RR = _csr(self.R.T @ self.R)
+        return RR if self.Q is None else _csr(self.Q + RR)
+
+    def explicit(self) -> "QP":
+        """The same problem with Q written out."""
+        return QP(n=self.n, m=self.m, Q=self.explicit_Q(), A=self.A, c=self.c, b=self.b,
+                  sense=self.sense, lb=self.lb, ub=self.ub, name=self.name + "_explicit",
+                  meta=self.meta)
 
     def csr_arrays(self, M):
         """(rowptr int64, col int32, val float64) of a CSR matrix, C-contiguous."""
@@ -184,12 +201,15 @@ def large_sparse(instance: int = 0, n: int = 1_000_000, m: int | None = None,
 
 
 def portfolio(instance: int = 0, n_assets: int = 200_000, k_factors: int = 1000,
-              f_density: float = 0.01) -> QP:
+              f_density: float = 0.01, infeasible: bool = False) -> QP:
     """Factor-model portfolio QP with diagonal Q.  Variables: weights w
     (n_assets) then factor exposures f (k_factors).  Q = diag(d) on w,
     d ~ U(0.01, 0.1), and I on f.  Rows: F w - f = 0 (F at f_density,
     N(0, 0.1)), then the budget row sum(w) = 1.  0 <= w <= 0.01, f free.
-    c = -mu on w with mu ~ N(0.05, 0.02), 0 on f."""
+    c = -mu on w with mu ~ N(0.05, 0.02), 0 on f.
+
+    ``infeasible`` asks the budget row for 0.01 n_assets + 1, more than the
+    box allows (certificate: the budget row's multiplier)."""
     rng = rng_for(FAM_PORTFOLIO, instance)
     na, k = n_assets, k_factors
     n = na + k
@@ -200,11 +220,79 @@ def portfolio(instance: int = 0, n_assets: int = 200_000, k_factors: int = 1000,
                         sp.hstack([sp.csr_matrix(np.ones((1, na))), sp.csr_matrix((1, k))])]))
     mu = rng.normal(0.05, 0.02, size=na)
     c = np.concatenate([-mu, np.zeros(k)])
-    b = np.concatenate([np.zeros(k), [1.0]])
+    b = np.concatenate([np.zeros(k), [0.01 * na + 1.0 if infeasible else 1.0]])
     lb = np.concatenate([np.zeros(na), np.full(k, -np.inf)])
     ub = np.concatenate([np.full(na, 0.01), np.full(k, np.inf)])
     return QP(n=n, m=k + 1, Q=Q, A=A, c=c, b=b, sense=b"E" * (k + 1), lb=lb, ub=ub,
-              name=f"portfolio_n{na}_k{k}")
+              name=f"portfolio_n{na}_k{k}" + ("_infeasible" if infeasible else ""))
+
+
+def portfolio_factored(instance: int = 0, n_assets: int = 200_000, k_factors: int = 1000,
+                       f_density: float = 0.01) -> QP:
+    """The factor-model portfolio of `portfolio` posed without factor
+    variables: Q = diag(d) + F'F given by its factors (P = diag(d), R = F),
+    the budget row sum(w) = 1 as the only row, 0 <= w <= 0.01, c = -mu.  Its
+    optimal w and objective are those of `portfolio` with the same seed
+    (f = F w eliminated)."""
+    q = portfolio(instance, n_assets, k_factors, f_density)
+    na, k = n_assets, k_factors
+    P = _csr(q.Q[:na, :na])
+    F = _csr(q.A[:k, :na])
+    A = _csr(q.A[k:, :na])
+    return QP(n=na, m=1, Q=P, A=A, c=q.c[:na].copy(), b=np.array([1.0]), sense=b"E",
+              lb=q.lb[:na].copy(), ub=q.ub[:na].copy(), name=f"portfolio_factored_n{na}_k{k}", R=F)
+
+
+def random_factored(instance: int = 0, n: int = 400, m: int = 150, k: int = 12,
+                    boxed: bool = True) -> QP:
+    """QP with Q = P + R'R: P sparse symmetric with a dominant positive
+    diagonal (about 4 off-diagonals per row), R (k x n) at 20 % density
+    N(0,1); A (m x n) at 3 % density, first half '=', second half '>=';
+    box [-1, 1] (or free when not `boxed`); b = A x0 - slack, x0 ~ U(-0.5, 0.5)."""
+    rng = rng_for(FAM_FACTORED, instance)
+    S = _sparse_normal(rng, n, n, 2.0 / n)
+    off = _csr(S + S.T)
+    off.setdiag(0.0)
+    off.eliminate_zeros()
+    P = _csr(off + sp.diags(np.asarray(abs(off).sum(axis=1)).ravel() + 0.05))
+    R = _sparse_normal(rng, k, n, 0.2)
+    A = _sparse_normal(rng, m, n, 0.03)
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    b = A @ x0
+    ne = m // 2
+    b[ne:] -= rng.uniform(0.0, 0.1, size=m - ne)
+    sense = (b"E" * ne) + (b"G" * (m - ne))
+    lb = np.full(n, -1.0) if boxed else np.full(n, -np.inf)
+    ub = np.full(n, 1.0) if boxed else np.full(n, np.inf)
+    return QP(n=n, m=m, Q=P, A=_csr(A), c=rng.normal(size=n), b=b, sense=sense, lb=lb, ub=ub,
+              name=f"random_factored{instance}", R=_csr(R))
+
+
+def served_stream(count: int, instance: int = 0, rate: float = 2000.0):
+    """A seeded stream of `count` requests for the server: Poisson arrivals at
+    `rate` per second; 60 % batched-MPC instances, 30 % random QPs of the
+    random_small family with n ~ U{1000..50000} (per-row nonzeros held),
+    10 % portfolios with n_assets ~ U{10000..100000} and max(1, n/200)
+    factors; 2 % of the requests are the infeasible variant of their family.
+    Returns (arrival offsets in seconds, list of QP)."""
+    rng = rng_for(FAM_SERVED, instance)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    kind = rng.choice(3, size=count, p=[0.6, 0.3, 0.1])
+    bad = rng.random(count) < 0.02
+    sizes = rng.integers(1000, 50001, size=count)
+    assets = rng.integers(10000, 100001, size=count)
+    qs = []
+    for i in range(count):
+        if kind[i] == 0:
+            qs.append(mpc(1_000_000 + instance * count + i, infeasible=bool(bad[i])))
+        elif kind[i] == 1:
+            qs.append(random_small(1_000_000 + instance * count + i, n=int(sizes[i]),
+                                   infeasible=bool(bad[i])))
+        else:
+            na = int(assets[i])
+            qs.append(portfolio(1_000_000 + instance * count + i, n_assets=na,
+                                k_factors=max(1, na // 200), infeasible=bool(bad[i])))
+    return np.cumsum(gaps), qs
 
 
 # ---------------------------------------------------------------------------

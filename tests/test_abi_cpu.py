@@ -202,3 +202,43 @@ def test_server_config_and_validation():
         L.qp_server_destroy(h)
     else:
         assert rc == P.ERR_DEVICE
+
+
+def test_factored_validation():
+    q = I.random_factored(0, n=20, m=5, k=3)
+    mk = lambda R, k=None: (lambda: P.qp_create_factored(q.n, q.m, q.Q, R, q.A, q.c, q.b, q.sense,
+                                                         q.lb, q.ub))
+    R = q.R.tolil()
+    R[0, 25 - 6] = 1.0                       # still in range: valid
+    import ctypes as C
+    L = P.lib()
+    h = C.c_void_p()
+    rp = np.ascontiguousarray(q.R.indptr, np.int64)
+    rj = np.ascontiguousarray(q.R.indices, np.int32)
+    rv = np.ascontiguousarray(q.R.data, np.float64)
+    rj_bad = rj.copy(); rj_bad[0] = q.n                      # column out of range
+    assert L.qp_create_factored(q.n, 0, None, None, None, 3, rp.ctypes.data_as(P._lp),
+                                rj_bad.ctypes.data_as(P._ip), rv.ctypes.data_as(P._dp), None, None,
+                                None, np.ascontiguousarray(q.c).ctypes.data_as(P._dp), None, None,
+                                None, None, C.byref(h)) == P.ERR_INVALID_ARG
+    assert L.qp_create_factored(q.n, 0, None, None, None, 0, rp.ctypes.data_as(P._lp),
+                                rj.ctypes.data_as(P._ip), rv.ctypes.data_as(P._dp), None, None,
+                                None, np.ascontiguousarray(q.c).ctypes.data_as(P._dp), None, None,
+                                None, None, C.byref(h)) == P.ERR_INVALID_ARG   # k = 0
+    try:
+        hh = P.qp_create_from(q)
+    except P.QPError as e:
+        assert e.code == P.ERR_DEVICE
+    else:
+        P.qp_destroy(hh)
+
+
+def test_batch_rejects_long_rows():
+    """A row (of A, A' or Q) longer than QP_BATCH_MAX_ROW is refused before
+    any device call: the batched kernel sums a row with one thread."""
+    from paper_2602_23967_amd.instances import pack
+    qs = [I.mpc(0, horizon=10), I.portfolio(0, n_assets=300, k_factors=3)]
+    big, vo, ro = pack(qs)
+    _bad(lambda: P.qp_batch_create(2, vo, ro, big.Q, big.A, big.c, big.b, big.sense, big.lb, big.ub),
+         P.ERR_INVALID_ARG)
+    assert "QP_BATCH_MAX_ROW" in P.qp_last_error()

@@ -38,7 +38,8 @@ def _unbounded_lp():
 def mix():
     qs = [I.mpc(i) for i in range(20)]
     qs += [I.mpc(100, infeasible=True), I.mpc(101, infeasible=True)]
-    qs += [I.portfolio(5, n_assets=3000, k_factors=20), I.tiny_lp(3), _unbounded_lp()]
+    # (a portfolio's budget row is longer than QP_BATCH_MAX_ROW: not batched)
+    qs += [I.tiny_lp(3), _unbounded_lp()]
     # non-diagonal Q: the inner boxed-CG solve runs inside the workgroup
     qs += [I.random_small(0), I.random_small(1, n=300), I.mixed_bounds(0), I.tiny(3, n=6, m=3),
            I.contradictory_rows(0), I.unbounded_qp(0)]
@@ -46,9 +47,11 @@ def mix():
 
 
 def test_batch_matches_oracle(torch, mix):
+    print(f"launch of {len(mix)} instances", flush=True)
     with P.BatchSolver(mix) as bs:
         st, secs = bs.solve()
         res = [bs.result(i) for i in range(len(mix))]
+    print(f"launch done in {secs:.2f} s", flush=True)
     for q, g in zip(mix, res):
         o = oracle.solve(q, max_iter=100000)
         assert g.status == o.status, (q.name, g.status_name, o.status_name)
@@ -71,7 +74,7 @@ def test_batch_matches_oracle(torch, mix):
 def test_batch_alone_equals_in_the_mix(torch, mix):
     """An instance's result does not depend on the other instances of the
     launch (bitwise)."""
-    picks = (3, 7, 21, 25, 27)
+    picks = (3, 7, 21, 24, 26)
     with P.BatchSolver(mix) as bs:
         bs.solve()
         together = [bs.result(i) for i in picks]

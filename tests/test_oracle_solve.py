@@ -278,3 +278,19 @@ def test_primal_residual_scale_uses_both_row_bounds():
     k = oracle.kkt(q, x, np.zeros(2))
     viol = max((A @ x - q.b).max(), 0.0)
     assert k["r_primal"] == pytest.approx(viol / 51.0, rel=1e-10)
+
+
+def test_factored_portfolio_equals_factor_variable_form():
+    """Eliminating f = F w turns the factor-variable portfolio into the
+    factored one: the oracle reaches the same w and objective on both."""
+    import paper_2602_23967_amd.instances as I
+    qf = I.portfolio_factored(7, n_assets=400, k_factors=8)
+    qv = I.portfolio(7, n_assets=400, k_factors=8)
+    e = qf.explicit()
+    Fd = qf.R.toarray()
+    assert np.allclose(e.Q.toarray(), qf.Q.toarray() + Fd.T @ Fd, rtol=0, atol=1e-15)
+    a = oracle.solve(e, tol=1e-9, max_iter=400000)
+    b = oracle.solve(qv, tol=1e-9, max_iter=400000)
+    assert a.status == b.status == oracle.OPTIMAL
+    assert a.info["primal_obj"] == pytest.approx(b.info["primal_obj"], rel=1e-7, abs=1e-9)
+    assert np.abs(a.x - b.x[:400]).max() <= 1e-5
