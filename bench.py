@@ -287,6 +287,8 @@ def main_serve(args, torch, P, I):
         for i, rid in enumerate(ids):
             srv.wait(rid)
             res.append(srv.result(rid))
+            if (i + 1) % 100 == 0:
+                log(f"{i + 1} requests done at {time.perf_counter() - t0:.1f}s")
         elapsed = time.perf_counter() - t0
     lat = np.array([tm["finished"] - tm["submitted"] for _, tm in res])
     first = min(tm["submitted"] for _, tm in res)
@@ -309,6 +311,8 @@ def main_serve(args, torch, P, I):
     for q in qs:
         if time.perf_counter() - ta > args.one_at_a_time_s:
             break
+        if n_one % 50 == 0:
+            log(f"one at a time: {n_one} solved")
         a = time.perf_counter()
         with P.Solver(q) as s1:
             s1.solve(p64)

@@ -28,6 +28,8 @@ __device__ __forceinline__ double uniform(double v)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Sum (bit j of MAXMASK clear) or max (bit set) of NR values over the
 // workgroup, in a fixed order; the result lands in every thread.
 template <int NR, unsigned MAXMASK>
@@ -105,6 +107,10 @@ __device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, co
     }
 }
 
+__device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
+                                const double* mval, const int* trp, const int* tcol, const double* tval,
+                                double tol, long long max_iter, double* v, double* w, double* u, double* lds);
+
 // ---- ||M_b||_2 by power iteration on M_b'M_b, one instance per workgroup ----
 __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const int* rowoff,
                                                    const int* coloff, const int* mrp,
@@ -119,16 +125,34 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(queue, 1);
         __syncthreads();
-        const int b = s_b;
+        const int b = uniform_int(s_b);
         __syncthreads();
         if (b >= count) return;
-        const int c0 = coloff[b], n = coloff[b + 1] - c0;
-        const int r0 = rowoff[b], m = rowoff[b + 1] - r0;
-        const int nnz = mrp[r0 + m] - mrp[r0];
-        if (m == 0 || nnz == 0 || (sel && !sel[b])) {
-            if (threadIdx.x == 0) out[b] = 0.0;
-            continue;
-        }
+        // every value that steers control flow around a barrier is moved to
+        // scalar registers: a branch the compiler sees as divergent runs both
+        // sides under an exec mask, and an empty-mask side whose loop is
+        // steered by readfirstlane of idle lanes would execute a different
+        // number of barriers in different waves
+        const int c0 = uniform_int(coloff[b]), n = uniform_int(coloff[b + 1]) - c0;
+        const int r0 = uniform_int(rowoff[b]), m = uniform_int(rowoff[b + 1]) - r0;
+        const int nnz = uniform_int(mrp[r0 + m]) - uniform_int(mrp[r0]);
+        const int skip = (sel != nullptr) ? (uniform_int(sel[b]) == 0) : 0;
+        const int active = uniform_int((m > 0 && nnz > 0 && !skip) ? 1 : 0);
+        double sig = 0.0;
+        if (active) sig = power_norm_wg(c0, n, r0, m, mrp, mcol, mval, trp, tcol, tval, tol, max_iter, v, w,
+                                        u, lds);
+        if (threadIdx.x == 0) out[b] = sig;
+        __syncthreads();
+    }
+}
+
+// ||M_b||_2 of one instance by power iteration on M_b'M_b (the whole
+// workgroup; every branch below is on workgroup-uniform values)
+__device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
+                                const double* mval, const int* trp, const int* tcol, const double* tval,
+                                double tol, long long max_iter, double* v, double* w, double* u, double* lds)
+{
+    {
         // start vector: SplitMix64 of the local index (seed 0), in [-1, 1)
         double acc[1] = {0.0};
         for (int j = threadIdx.x; j < n; j += TPB) {
@@ -169,8 +193,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
             if (fabs(sig - prev) <= tol * sig) break;
             prev = sig;
         }
-        if (threadIdx.x == 0) out[b] = sig;
-        __syncthreads();
+        return sig;
     }
 }
 
@@ -179,8 +202,12 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
 template <bool F32>
 __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds)
 {
-    const int v0 = B.voff[b], n = B.voff[b + 1] - v0;
-    const int r0 = B.roff[b], m = B.roff[b + 1] - r0;
+    // per-instance values in scalar registers: the branches on them (closed
+    // form vs inner solve, certificates) must be seen as uniform, or the
+    // skipped side runs under an empty exec mask with its barrier count
+    // steered by idle lanes
+    const int v0 = uniform_int(B.voff[b]), n = uniform_int(B.voff[b + 1]) - v0;
+    const int r0 = uniform_int(B.roff[b]), m = uniform_int(B.roff[b + 1]) - r0;
     const int tid = threadIdx.x;
     double* x = B.x + v0;   double* xa = B.xa + v0; double* xt = B.xt + v0;
     double* xbar = B.xbar;  double* aty = B.aty + v0; double* d = B.d + v0;
@@ -191,9 +218,10 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     const double* lc = B.lc + r0; const double* uc = B.uc + r0;
 
     double* rhs = B.rhs + v0; double* g = B.g + v0; double* p = B.p + v0; double* hp = B.hp + v0;
-    const double eta = B.eta[b], omega0 = B.omega0[b], normq = B.normq[b];
+    const double eta = uniform(B.eta[b]), omega0 = uniform(B.omega0[b]), normq = uniform(B.normq[b]);
     double omega = omega0, tau = eta / omega, sigma = eta * omega, it = 1.0 / tau;
-    const int unb = B.unb[b], qgen = B.qgen[b];
+    const int unb = uniform_int(B.unb[b]), qgen = uniform_int(B.qgen[b]);
+    const double cmax = uniform(B.cmax[b]), bscale = uniform(B.bscale[b]), gammaq = uniform(B.gammaq[b]);
     double eps = INFINITY;
     long long inner_total = 0;
 
@@ -265,8 +293,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 }
             }
             wg_reduce<16, kinds>(a, lds);
-            const double cmax = B.cmax[b];
-            rp_ = a[4] / B.bscale[b];
+            rp_ = a[4] / bscale;
             double sd = a[9] > a[0] ? a[9] : a[0];
             sd = sd > cmax ? sd : cmax;
             rd_ = a[8] / (1.0 + sd);
@@ -284,7 +311,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 pinf = imp > 1e-9 * (a[3] + ptil_abs) && a[1] <= P.eps_inf * imp;
             }
             if (k > 0 && unb && d_max > 0.0 && isfinite(d_max) && cd / d_max < -P.tol) {
-                const double v1 = a[7] / d_max, v2 = a[15] / d_max / B.gammaq[b];
+                const double v1 = a[7] / d_max, v2 = a[15] / d_max / gammaq;
                 dinf = (v1 > v2 ? v1 : v2) <= P.eps_inf;
             }
             int restart = 0;
@@ -503,7 +530,7 @@ __global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
         __syncthreads();
-        const int b = s_b;
+        const int b = uniform_int(s_b);
         __syncthreads();
         if (b >= B.count) return;
         batch_solve_one<F32>(B, P, b, lds);
