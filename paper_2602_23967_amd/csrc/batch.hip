@@ -92,11 +92,39 @@ __device__ __forceinline__ double row_dot(const int* rp, const int* col, const d
     return s;
 }
 
-// a bulk product of the iteration: FP32 values, operand rounded to FP32 and
-// an FP32 sum in mixed precision, else the FP64 row_dot
+// A bulk product of the iteration.  FP64: the row of M times x.  Mixed
+// precision: the product is split around a reference point x_ref whose
+// product ref = (M x_ref)_row is known in FP64 (from the last check):
+// ref + M (x - x_ref) with FP32 values, the difference rounded to FP32 and
+// an FP32 sum, so the FP32 rounding scales with the movement since the
+// check and not with the iterate.
 template <bool F32>
 __device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, const double* val,
-                                               const float* val32, const double* x, int row)
+                                               const float* val32, const double* x, const double* xref,
+                                               double ref, int row)
+{
+    if constexpr (F32) {
+        float s = 0.0f;
+        for (int q = rp[row]; q < rp[row + 1]; ++q) {
+            const int j = col[q];
+            s += val32[q] * (float)(x[j] - xref[j]);
+        }
+        return ref + (double)s;
+    } else {
+        return row_dot(rp, col, val, x, row);
+    }
+}
+
+__device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
+                                const double* mval, const int* trp, const int* tcol, const double* tval,
+                                double tol, long long max_iter, double* v, double* w, double* u, double* lds);
+
+// the inner step's product H p: FP32 values, direction and sum in mixed
+// precision (the inner solve re-forms its gradient in FP64 at every
+// subproblem and after every expansion step)
+template <bool F32>
+__device__ __forceinline__ double hp_dot(const int* rp, const int* col, const double* val,
+                                         const float* val32, const double* x, int row)
 {
     if constexpr (F32) {
         float s = 0.0f;
@@ -106,10 +134,6 @@ __device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, co
         return row_dot(rp, col, val, x, row);
     }
 }
-
-__device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
-                                const double* mval, const int* trp, const int* tcol, const double* tval,
-                                double tol, long long max_iter, double* v, double* w, double* u, double* lds);
 
 // ---- ||M_b||_2 by power iteration on M_b'M_b, one instance per workgroup ----
 __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const int* rowoff,
@@ -225,12 +249,18 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     double eps = INFINITY;
     long long inner_total = 0;
 
+    // mixed precision: reference point (x_ref, y_ref) and its FP64 products
+    // A x_ref (axref) and A' y_ref (aty, written by every check); zero until
+    // the first check
+    double* xref = B.xref; double* yref = B.yref; double* axref = B.axref + r0;
     for (int i = tid; i < n; i += TPB) {
         const double v = clampd(0.0, lv[i], uv[i]);
         x[i] = v; xa[i] = v; xt[i] = v;
+        if constexpr (F32) { xref[v0 + i] = 0.0; aty[i] = 0.0; }
     }
     for (int j = tid; j < m; j += TPB) {
         y[j] = 0.0; ya[j] = 0.0; yt[r0 + j] = 0.0;
+        if constexpr (F32) { yref[r0 + j] = 0.0; axref[j] = 0.0; }
     }
     __syncthreads();
 
@@ -263,6 +293,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             }
             for (int j = tid; j < m; j += TPB) {
                 const double s = row_dot(B.arp, B.acol, B.aval, B.xt, r0 + j);
+                if constexpr (F32) axref[j] = s;
                 a[4] = rcomb(R_MAX, a[4], fabs(s - clampd(s, lc[j], uc[j])));
                 const double yj = yt[r0 + j];
                 a[5] += supp(yj, lc[j], uc[j]);
@@ -291,6 +322,12 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     const double qdv = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.d, v0 + i) : qd[i] * d[i];
                     a[15] = rcomb(R_MAX, a[15], fabs(qdv));
                 }
+            }
+            if constexpr (F32) {
+                // the new reference point: (x_T, y_T), whose products with A
+                // and A' this check computed in FP64
+                for (int i = tid; i < n; i += TPB) xref[v0 + i] = xt[i];
+                for (int j = tid; j < m; j += TPB) yref[r0 + j] = yt[r0 + j];
             }
             wg_reduce<16, kinds>(a, lds);
             rp_ = a[4] / bscale;
@@ -360,7 +397,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         if (!qgen) {
             // ---- primal step: closed form (Section 2.2) and x_bar -----------------
             for (int i = tid; i < n; i += TPB) {
-                const double s = row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, v0 + i);
+                const double s = row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
                 const double xi = x[i];
                 const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
                 xt[i] = v;
@@ -372,10 +409,11 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             const double abar = P.abar_scale / (normq + it);
             double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
             for (int i = tid; i < n; i += TPB) {
-                const double r = x[i] * it - c[i] - row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, v0 + i);
+                const double r = x[i] * it - c[i] -
+                                 row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
                 rhs[i] = r;
                 const double xi = xt[i];
-                const double gi = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.xt, v0 + i) + it * xi - r;
+                const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - r;
                 g[i] = gi;
                 const Split sp = split(xi, gi, lv[i], uv[i], abar);
                 st[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -399,7 +437,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 double hs[3] = {0.0, 0.0, INFINITY};   // p'Hp, g'p, feasible step
                 for (int i = tid; i < n; i += TPB) {
                     const double pi = p[i], xi = xt[i];
-                    const double h = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i) + it * pi;
+                    const double h = hp_dot<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i) + it * pi;
                     hp[i] = h;
                     hs[0] += pi * h;
                     hs[1] += g[i] * pi;
@@ -440,7 +478,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     us[0] = us[1] = us[2] = 0.0;
                     for (int i = tid; i < n; i += TPB) {
                         const double xi = xt[i];
-                        const double gi = row_dot_bulk<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.xt, v0 + i) + it * xi - rhs[i];
+                        const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - rhs[i];
                         g[i] = gi;
                         const Split sp = split(xi, gi, lv[i], uv[i], abar);
                         us[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -465,7 +503,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         double a[7] = {0, 0, 0, 0, 0, 0, 0};
         constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
         for (int j = tid; j < m; j += TPB) {
-            const double s = row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, r0 + j);
+            const double s = row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j);
             const double yj = y[j], l = lc[j], u = uc[j];
             const double v = yj / sigma + s;
             const double ytj = sigma * (v - clampd(v, l, u));

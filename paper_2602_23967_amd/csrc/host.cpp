@@ -320,6 +320,14 @@ int set_precision(qp_handle* h, int precision)
     } else {
         S.A.val32 = S.AT.val32 = S.Q.val32 = S.R.val32 = nullptr;
     }
+    S.mixed = precision == QP_PRECISION_MIXED;
+    if (S.mixed && !S.xref) {
+        int rc;
+        if ((rc = dalloc(h, &S.xref, (size_t)h->n)) || (rc = dalloc(h, &S.atyref, (size_t)h->n)) ||
+            (rc = dalloc(h, &S.yref, (size_t)h->m)) || (rc = dalloc(h, &S.axref, (size_t)h->m)) ||
+            (rc = dalloc(h, &S.dxb32, (size_t)h->n)) || (rc = dalloc(h, &S.dy32, (size_t)h->m)))
+            return rc;
+    }
     return 0;
 }
 
@@ -894,6 +902,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     setup_ctrl(h, p, c);
     HIPCHK(hipMemcpyAsync(S.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     HIPCHK(launch_init_start(S, s));
+    HIPCHK(launch_ref_zero(S, s));
     HIPCHK(hipStreamSynchronize(s));
     h->hstat[0] = 0;
     h->hstat[1] = 0;
@@ -908,6 +917,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                     Timed t(h, QP_FAM_CHECK);
                     HIPCHK(launch_check(S, S.xt, S.yt, 1, h->has_unbounded_x, s));
                     HIPCHK(launch_restart_copy(S, s));
+                    HIPCHK(launch_ref_update(S, s));
                 }
                 HIPCHK(hipStreamSynchronize(s));
                 int st = 0;
@@ -1052,6 +1062,7 @@ int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double
     DevState& S = h->S;
     hipStream_t s = h->stream;
     qp_params p = qp_params_default();
+    if (int rc = set_precision(h, QP_PRECISION_FP64)) return rc;
     Ctrl c;
     setup_ctrl(h, p, c);
     c.tau = tau;
@@ -1296,10 +1307,10 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
         (rc = bupload(bt, &B.lv, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv, uvv.data(), (size_t)n)) ||
         (rc = bupload(bt, &B.lc, lcv.data(), (size_t)m)) || (rc = bupload(bt, &B.uc, ucv.data(), (size_t)m)))
         return bail(rc);
-    double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d, &B.rhs, &B.g, &B.p, &B.hp};
+    double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d, &B.rhs, &B.g, &B.p, &B.hp, &B.xref};
     for (double** p : nv)
         if ((rc = balloc(bt, p, (size_t)n))) return bail(rc);
-    double** mv[] = {&B.y, &B.ya, &B.yt, &B.ytil};
+    double** mv[] = {&B.y, &B.ya, &B.yt, &B.ytil, &B.yref, &B.axref};
     for (double** p : mv)
         if ((rc = balloc(bt, p, (size_t)m))) return bail(rc);
     if ((rc = balloc(bt, &B.queue, 1)) || (rc = balloc(bt, &B.out, (size_t)count))) return bail(rc);

@@ -66,34 +66,22 @@ struct SumOne {
 // the two kernel shapes
 // ---------------------------------------------------------------------------
 
-// F32: products and row sums in single precision from the FP32 copy of the
-// values (the operand is rounded to FP32 as it is gathered); the row sum is
-// widened to FP64 before the epilogue, which keeps its arithmetic in FP64
-template <class E, bool F32>
-__global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
+// One row block (or long-row segment) of a product, with products and sums
+// in T.  T = float is the mixed-precision form: FP32 values, the operand the
+// epilogue hands out in FP32 (for the iteration's products, the difference
+// between the operand and the reference point of the last check), FP32 row
+// sums widened to FP64, plus the epilogue's FP64 reference product of the
+// row.  Partial sums of column parts and of long-row segments are stored
+// without the reference; the passes that complete those rows add it.
+template <class E, class T>
+__device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T* val, T* prod,
+                                           const int* srp, double* lds,
+                                           double (&acc)[E::NR > 0 ? E::NR : 1])
 {
-    using T = typename std::conditional<F32, float, double>::type;
-    constexpr int NR = E::NR > 0 ? E::NR : 1;
-    __shared__ T prod[NNZ_CAP];
-    __shared__ int srp[PART_ROWS_CAP + 1];   // the block's row pointers, relative to k0
-    __shared__ double lds[NR * (TPB / 64)];
-    E e = epi;
-    if (e.skip()) return;
-    e.init();
+    constexpr bool F32 = std::is_same<T, float>::value;
     const BlkDesc d = M.blk[blockIdx.x];
-    double acc[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
-
     const int cnt = d.k1 - d.k0;
-    if (d.nrows > 0) {
-        const int* rp = M.rowptr + (size_t)d.lr * (M.rows + 1) + d.row0;
-        for (int r = threadIdx.x; r <= d.nrows; r += TPB) srp[r] = rp[r] - d.k0;
-    }
     {
-        const T* val;
-        if constexpr (F32) val = M.val32;
-        else val = M.val;
         int cj[NNZ_CAP / TPB];
         T av[NNZ_CAP / TPB];
 #pragma unroll
@@ -112,7 +100,10 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
-            if (cj[i] >= 0) prod[q] = av[i] * static_cast<T>(e.xval(cj[i]));
+            if (cj[i] >= 0) {
+                if constexpr (F32) prod[q] = av[i] * e.xval32(cj[i]);
+                else prod[q] = av[i] * e.xval(cj[i]);
+            }
         }
     }
     __syncthreads();
@@ -130,6 +121,7 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
             for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
             if (lane == 0) {
                 if (partial) M.ypart[(size_t)d.lr * M.rows + row] = (double)s;
+                else if constexpr (F32) e.row(row, (double)s + e.rowref(row), acc);
                 else e.row(row, (double)s, acc);
             }
         }
@@ -140,6 +132,36 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
         block_reduce<SumOne>(s, lds);
         if (threadIdx.x == 0) M.seg_part[d.seg_base + d.seg] = s[0];
     }
+}
+
+// F32: the mixed-precision form for the iteration's own products (E::BULK)
+// when the epilogue asks for it (use32(): a mixed solve, and not a product
+// that must be exact, such as the gradient after an expansion step)
+template <class E, bool F32>
+__global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
+{
+    constexpr int NR = E::NR > 0 ? E::NR : 1;
+    __shared__ double prodbuf[NNZ_CAP];
+    __shared__ int srp[PART_ROWS_CAP + 1];   // the block's row pointers, relative to k0
+    __shared__ double lds[NR * (TPB / 64)];
+    E e = epi;
+    if (e.skip()) return;
+    e.init();
+    const BlkDesc d = M.blk[blockIdx.x];
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
+    if (d.nrows > 0) {
+        const int* rp = M.rowptr + (size_t)d.lr * (M.rows + 1) + d.row0;
+        for (int r = threadIdx.x; r <= d.nrows; r += TPB) srp[r] = rp[r] - d.k0;
+    }
+    bool f32 = false;
+    if constexpr (F32) f32 = e.use32();
+    if constexpr (F32) {
+        if (f32) spmv_block<E, float>(M, e, M.val32, reinterpret_cast<float*>(prodbuf), srp, lds, acc);
+    }
+    if (!f32) spmv_block<E, double>(M, e, M.val, prodbuf, srp, lds, acc);
+
     if constexpr (E::NR > 0) {
         if (M.nparts > 1) return;   // the row pass reduces
         block_reduce<E>(acc, lds);
@@ -168,6 +190,7 @@ __global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
         double s = 0.0;
 #pragma unroll
         for (int p = 0; p < NPARTS; ++p) s += M.ypart[(size_t)p * M.rows + i];
+        if (e.use32()) s += e.rowref((int)i);
         e.row((int)i, s, acc);
     }
     if constexpr (E::NR > 0) {
@@ -196,6 +219,7 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
         const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
         double total = 0.0;
         for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
+        if (e.use32()) total += e.rowref(row);
         e.row(row, total, acc);
     }
     if constexpr (E::NR > 0) {
@@ -262,6 +286,11 @@ struct EpiBase {
     Ctrl* ctrl;
     __device__ bool skip() const { return false; }
     __device__ void init() {}
+    // mixed precision (BULK epilogues): whether this launch takes the FP32
+    // form, the operand it then gathers, and the FP64 reference product of a row
+    __device__ bool use32() const { return false; }
+    __device__ float xval32(int) const { return 0.0f; }
+    __device__ double rowref(int) const { return 0.0; }
     __device__ static int kind(int) { return R_SUM; }
     __device__ void finalize(const double*) const {}
 };
@@ -292,15 +321,25 @@ struct EpiProx : EpiBase {
     static constexpr int NR = 0;
     const double *y, *x, *c, *qd, *lv, *uv;
     double *xt, *xbar;
+    // mixed precision: A' y = A' y_ref + A'(y - y_ref) (dy32, aty_ref), and
+    // x_bar - x_ref is written for the dual step's product
+    const float* dy32 = nullptr;
+    const double *atyref = nullptr, *xref = nullptr;
+    float* dxb32 = nullptr;
     double it;
     __device__ void init() { it = ctrl->inv_tau; }
     __device__ double xval(int j) const { return y[j]; }
+    __device__ bool use32() const { return dy32 != nullptr; }
+    __device__ float xval32(int j) const { return dy32[j]; }
+    __device__ double rowref(int i) const { return atyref[i]; }
     __device__ void row(int i, double s, Acc<NR>) const
     {
         const double xi = x[i];
         const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
         xt[i] = v;
-        xbar[i] = 2.0 * v - xi;
+        const double xb = 2.0 * v - xi;
+        xbar[i] = xb;
+        if (dxb32) dxb32[i] = (float)(xb - xref[i]);
     }
 };
 
@@ -309,7 +348,14 @@ struct EpiXbar : EpiBase {
     static constexpr int NR = 0;
     const double *xt, *x;
     double* xbar;
-    __device__ void elem(long long i, Acc<NR>) const { xbar[i] = 2.0 * xt[i] - x[i]; }
+    const double* xref = nullptr;   // mixed precision: also x_bar - x_ref in FP32
+    float* dxb32 = nullptr;
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        const double xb = 2.0 * xt[i] - x[i];
+        xbar[i] = xb;
+        if (dxb32) dxb32[i] = (float)(xb - xref[i]);
+    }
 };
 
 // x <- clip(x, l_v, u_v)
@@ -326,9 +372,14 @@ struct EpiRhs : EpiBase {
     static constexpr int NR = 0;
     const double *y, *x, *c;
     double* rhs;
+    const float* dy32 = nullptr;
+    const double* atyref = nullptr;
     double it;
     __device__ void init() { it = ctrl->inv_tau; }
     __device__ double xval(int j) const { return y[j]; }
+    __device__ bool use32() const { return dy32 != nullptr; }
+    __device__ float xval32(int j) const { return dy32[j]; }
+    __device__ double rowref(int i) const { return atyref[i]; }
     __device__ void row(int i, double s, Acc<NR>) const { rhs[i] = x[i] * it - c[i] - s; }
 };
 
@@ -343,6 +394,11 @@ struct EpiRhsGrad : EpiBase {
     double *rhs, *g;
     unsigned long long* dstat;
     long long seq;
+    const float* dy32 = nullptr;
+    const double* atyref = nullptr;
+    __device__ bool use32() const { return dy32 != nullptr; }
+    __device__ float xval32(int j) const { return dy32[j]; }
+    __device__ double rowref(int i) const { return atyref[i]; }
     double it, dit, abar;
     __device__ void init()
     {
@@ -378,8 +434,7 @@ struct EpiRhsGrad : EpiBase {
 // gradient of the subproblem at the warm start (feasible): g = Q x + x/tau - rhs,
 // with split statistics; finalize starts the inner solve
 struct EpiGinit : EpiBase {
-    static constexpr bool BULK = true;
-    static constexpr int NR = 3;
+    static constexpr int NR = 3;   // the exact gradient: FP64 in every precision
     const double* xt;
     const double *rhs, *lv, *uv;
     double* g;
@@ -422,6 +477,9 @@ struct EpiStepA : EpiBase {
     long long seq;
     double it, abar;
     int ng;
+    int mixed = 0;   // mixed precision: H p in FP32; the gradient after an expansion stays FP64
+    __device__ bool use32() const { return mixed && !ng; }
+    __device__ float xval32(int j) const { return (float)p[j]; }
     __device__ static int kind(int j) { return j == 3 ? R_MIN : R_SUM; }
     __device__ bool skip() const { return ctrl->done != 0; }
     __device__ void init() { it = ctrl->inv_tau; abar = ctrl->abar; ng = ctrl->need_g; }
@@ -552,6 +610,14 @@ struct EpiDual : EpiBase {
     const double *xbar, *ya, *lc, *uc;
     double *y, *yt, *ytil;
     int store;
+    // mixed precision: A x_bar = A x_ref + A(x_bar - x_ref) (dxb32, axref), and
+    // y - y_ref is written for the next primal step's product
+    const float* dxb32 = nullptr;
+    const double *axref = nullptr, *yref = nullptr;
+    float* dy32 = nullptr;
+    __device__ bool use32() const { return dxb32 != nullptr; }
+    __device__ float xval32(int j) const { return dxb32[j]; }
+    __device__ double rowref(int i) const { return axref[i]; }
     double sigma, w, wa, th;
     int halpern;
     __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
@@ -573,7 +639,9 @@ struct EpiDual : EpiBase {
         const double dy = yti - yi;
         a[0] += dy * dy;
         yt[i] = yti;
-        y[i] = halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
+        const double yn = halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
+        y[i] = yn;
+        if (dy32) dy32[i] = (float)(yn - yref[i]);
         if (store) {
             const double yy = projY(dy, l, u);
             ytil[i] = yy;
@@ -664,6 +732,9 @@ struct EpiTailHp : EpiBase {
     const double *p, *xt;
     double *ptail, *xtail;
     int ng;
+    int mixed = 0;
+    __device__ bool use32() const { return mixed && !ng; }
+    __device__ float xval32(int j) const { return (float)p[j]; }
     __device__ bool skip() const { return ctrl->done != 0; }
     __device__ void init() { ng = ctrl->need_g; }
     __device__ double xval(int j) const { return ng ? xt[j] : p[j]; }
@@ -721,11 +792,13 @@ struct EpiAty : EpiBase {
     static constexpr int NR = 1;
     const double* y;
     double* aty;
+    double* atyref = nullptr;   // mixed precision: the reference product A' y_T
     __device__ static int kind(int) { return R_MAX; }
     __device__ double xval(int j) const { return y[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
         aty[i] = s;
+        if (atyref) atyref[i] = s;
         a[0] = rcomb(R_MAX, a[0], fabs(s));
     }
     __device__ void finalize(const double* t) const { ctrl->aty_max = t[0]; }
@@ -735,10 +808,12 @@ struct EpiAty : EpiBase {
 struct EpiAx : EpiBase {
     static constexpr int NR = 3;
     const double *x, *y, *ya, *lc, *uc;
+    double* axref = nullptr;   // mixed precision: the reference product A x_T
     __device__ static int kind(int j) { return j == 0 ? R_MAX : R_SUM; }
     __device__ double xval(int j) const { return x[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
+        if (axref) axref[i] = s;
         const double l = lc[i], u = uc[i], yi = y[i];
         a[0] = rcomb(R_MAX, a[0], fabs(s - clampd(s, l, u)));
         a[1] += supp(yi, l, u);
@@ -879,6 +954,46 @@ struct EpiRestart : EpiBase {
             const long long j = i - n;
             y[j] = yt[j];
             ya[j] = yt[j];
+        }
+    }
+};
+
+// mixed precision: the new reference point (x_T, y_T) after a check, and
+// y - y_ref for the next primal step's product
+struct EpiRefUpdate : EpiBase {
+    static constexpr int NR = 0;
+    const double *xt, *yt, *y;
+    double *xref, *yref;
+    float* dy32;
+    int n;
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        if (i < n) {
+            xref[i] = xt[i];
+        } else {
+            const long long j = i - n;
+            yref[j] = yt[j];
+            dy32[j] = (float)(y[j] - yt[j]);
+        }
+    }
+};
+
+// mixed precision: reference point and products zero before the first check
+struct EpiRefZero : EpiBase {
+    static constexpr int NR = 0;
+    double *xref, *atyref, *yref, *axref;
+    float* dy32;
+    int n;
+    __device__ void elem(long long i, Acc<NR>) const
+    {
+        if (i < n) {
+            xref[i] = 0.0;
+            atyref[i] = 0.0;
+        } else {
+            const long long j = i - n;
+            yref[j] = 0.0;
+            axref[j] = 0.0;
+            dy32[j] = 0.0f;
         }
     }
 };
@@ -1028,6 +1143,7 @@ hipError_t launch_prox_diag(const DevState& S, hipStream_t s)
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.qd = S.qd; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt;
     e.xbar = S.xbar;
+    if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; e.xref = S.xref; e.dxb32 = S.dxb32; }
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -1036,6 +1152,7 @@ hipError_t launch_rhs(const DevState& S, hipStream_t s)
     EpiRhs e{};
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.rhs = S.rhs;
+    if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; }
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -1045,6 +1162,7 @@ hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s)
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.xt = S.xt; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.g = S.g;
     e.dstat = S.dstat; e.seq = seq;
+    if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; }
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -1066,7 +1184,7 @@ hipError_t launch_tail(const DevState& S, const double* v, double* tail, bool bu
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s)
 {
     if (S.R.rows) {
-        hipError_t err = launch_tail(S, S.xt, S.xt + S.n, true, s);
+        hipError_t err = launch_tail(S, S.xt, S.xt + S.n, false, s);
         if (err != hipSuccess) return err;
     }
     EpiGinit e{};
@@ -1089,14 +1207,14 @@ hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s)
     if (S.R.rows) {
         EpiTailHp t{};
         t.ctrl = S.ctrl;
-        t.p = S.p; t.xt = S.xt; t.ptail = S.p + S.n; t.xtail = S.xt + S.n;
+        t.p = S.p; t.xt = S.xt; t.ptail = S.p + S.n; t.xtail = S.xt + S.n; t.mixed = S.mixed;
         hipError_t err = run_spmv(S, S.R, t, s);
         if (err != hipSuccess) return err;
     }
     EpiStepA e{};
     e.ctrl = S.ctrl;
     e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
-    e.dstat = S.dstat; e.seq = seq;
+    e.dstat = S.dstat; e.seq = seq; e.mixed = S.mixed;
     return run_spmv(S, S.Q, e, s);
 }
 
@@ -1114,6 +1232,7 @@ hipError_t launch_xbar(const DevState& S, hipStream_t s)
     EpiXbar e{};
     e.ctrl = S.ctrl;
     e.xt = S.xt; e.x = S.x; e.xbar = S.xbar;
+    if (S.mixed) { e.xref = S.xref; e.dxb32 = S.dxb32; }
     return run_vec(S, S.n, e, s);
 }
 
@@ -1131,6 +1250,7 @@ hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s)
     e.ctrl = S.ctrl;
     e.xbar = S.xbar; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
+    if (S.mixed) { e.dxb32 = S.dxb32; e.axref = S.axref; e.yref = S.yref; e.dy32 = S.dy32; }
     return run_spmv(S, S.A, e, s);
 }
 
@@ -1168,10 +1288,12 @@ hipError_t launch_check(const DevState& S, const double* x, const double* y, int
     EpiAty et{};
     et.ctrl = S.ctrl;
     et.y = y; et.aty = S.aty;
+    if (full && S.mixed) et.atyref = S.atyref;
     if ((err = run_spmv(S, S.AT, et, s)) != hipSuccess) return err;
     EpiAx ex{};
     ex.ctrl = S.ctrl;
     ex.x = x; ex.y = y; ex.ya = full ? S.ya : nullptr; ex.lc = S.lc; ex.uc = S.uc;
+    if (full && S.mixed) ex.axref = S.axref;
     if ((err = run_spmv(S, S.A, ex, s)) != hipSuccess) return err;
     if (S.R.rows) {
         // the operand needs room for its tail: x_T has it, any other x is copied
@@ -1196,6 +1318,24 @@ hipError_t launch_restart_copy(const DevState& S, hipStream_t s)
     EpiRestart e{};
     e.ctrl = S.ctrl;
     e.xt = S.xt; e.yt = S.yt; e.x = S.x; e.xa = S.xa; e.y = S.y; e.ya = S.ya; e.n = S.n;
+    return run_vec(S, (long long)S.n + S.m, e, s);
+}
+
+hipError_t launch_ref_update(const DevState& S, hipStream_t s)
+{
+    if (!S.mixed) return hipSuccess;
+    EpiRefUpdate e{};
+    e.ctrl = S.ctrl;
+    e.xt = S.xt; e.yt = S.yt; e.y = S.y; e.xref = S.xref; e.yref = S.yref; e.dy32 = S.dy32; e.n = S.n;
+    return run_vec(S, (long long)S.n + S.m, e, s);
+}
+
+hipError_t launch_ref_zero(const DevState& S, hipStream_t s)
+{
+    if (!S.mixed) return hipSuccess;
+    EpiRefZero e{};
+    e.ctrl = S.ctrl;
+    e.xref = S.xref; e.atyref = S.atyref; e.yref = S.yref; e.axref = S.axref; e.dy32 = S.dy32; e.n = S.n;
     return run_vec(S, (long long)S.n + S.m, e, s);
 }
 

@@ -117,6 +117,12 @@ struct DevState {
     // work vectors
     double *rhs = nullptr, *g = nullptr, *p = nullptr, *hp = nullptr, *aty = nullptr;
     double *dx = nullptr, *ytil = nullptr, *v1 = nullptr, *v2 = nullptr, *xbar = nullptr;
+    // mixed precision: the reference point of the last check (x_ref, y_ref),
+    // its FP64 products A x_ref, A' y_ref, and the FP32 differences
+    // x_bar - x_ref, y - y_ref that the iteration's products gather
+    int mixed = 0;
+    double *xref = nullptr, *yref = nullptr, *axref = nullptr, *atyref = nullptr;
+    float *dxb32 = nullptr, *dy32 = nullptr;
     Ctrl* ctrl = nullptr;
     double* partials = nullptr;
     hipEvent_t* tev = nullptr;             // when set: events around the next main kernel
@@ -147,6 +153,10 @@ hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
                         hipStream_t s);
 hipError_t launch_restart_copy(const DevState& S, hipStream_t s);
+// mixed precision only (no-ops otherwise): take (x_T, y_T) as the new
+// reference point after a check; zero the reference before the first check
+hipError_t launch_ref_update(const DevState& S, hipStream_t s);
+hipError_t launch_ref_zero(const DevState& S, hipStream_t s);
 // power iteration pieces: v <- unit start vector; w = M v with ||w||^2; v = w / ||w||
 hipError_t launch_power_start(const DevState& S, double* v, int len, hipStream_t s);
 hipError_t launch_spmv_norm(const DevState& S, const CsrDev& M, const double* x, double* y,
@@ -200,6 +210,8 @@ struct BatchDev {
     double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
     double *xbar = nullptr, *aty = nullptr, *d = nullptr, *ytil = nullptr;
     double *rhs = nullptr, *g = nullptr, *p = nullptr, *hp = nullptr;
+    // mixed precision: the reference point of the last check and A x_ref
+    double *xref = nullptr, *yref = nullptr, *axref = nullptr;
     BatchOut* out = nullptr;
 };
 
