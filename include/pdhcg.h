@@ -101,10 +101,11 @@ enum {
     QP_FAM_SPMV_HP = 0,   /* inner step: H p (or H x after an expansion), fused */
     QP_FAM_UPDATE = 1,    /* inner step: x, g update with reductions */
     QP_FAM_DIR = 2,       /* inner step: next direction */
-    QP_FAM_RHS = 3,       /* A'y fused with the subproblem right-hand side (or closed form) */
+    QP_FAM_RHS = 3,       /* A'y fused with the subproblem right-hand side (or, for a diagonal
+                             Q, with the closed-form step, x_bar and Halpern on x) */
     QP_FAM_GINIT = 4,     /* gradient at the warm start */
     QP_FAM_DUAL = 5,      /* A x_bar fused with the dual step and Halpern on y */
-    QP_FAM_HALPX = 6,     /* Halpern on x, movement norms, tolerance update */
+    QP_FAM_HALPX = 6,     /* after the inner solve: x_bar, Halpern on x, movement, tolerance */
     QP_FAM_CHECK = 7,     /* KKT / infeasibility / restart checks */
     QP_NFAM = 8
 };

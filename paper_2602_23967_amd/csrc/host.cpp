@@ -935,7 +935,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
         const int next_check = ((k + 1) % p.check_every == 0) || (k + 1 >= p.max_iter);
         if (S.qdiag) {
             Timed t(h, QP_FAM_RHS);
-            HIPCHK(launch_prox_diag(S, s));
+            HIPCHK(launch_prox_diag(S, next_check, s));
         } else {
             // the gradient is formed with a product with Q at the first
             // iteration and after every check (bounds the drift of the
@@ -947,15 +947,12 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
             }
             int rc = inner_solve(h, gseq, p.inner_lag, exact);
             if (rc) return rc;
-            HIPCHK(launch_xbar(S, s));
+            Timed t(h, QP_FAM_HALPX);
+            HIPCHK(launch_xbar(S, next_check, s));
         }
         {
             Timed t(h, QP_FAM_DUAL);
             HIPCHK(launch_dual(S, next_check, s));
-        }
-        {
-            Timed t(h, QP_FAM_HALPX);
-            HIPCHK(launch_halpx(S, next_check, s));
         }
         ++k;
     }

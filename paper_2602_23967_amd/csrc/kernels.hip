@@ -314,25 +314,76 @@ __device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long lo
     post_status(dstat, seq, c->done);
 }
 
+// Reflected Halpern average of x (Section 3.1) for one row, fused into the
+// kernel that produces x_T: x <- w((1+theta) x_T - theta x) + wa x_anchor,
+// the movement ||x_T - x||^2 and, when a check follows, the pieces of the
+// unboundedness certificate d = proj_Recc(X)(x_T - x) (Section 5).
+struct HalpernX {
+    const double *xa, *c, *lv, *uv;
+    double *x, *d;
+    int store;
+    double w, wa, th;
+    int halpern, unb;
+    __device__ void init(const Ctrl* ctrl)
+    {
+        const double t = (double)ctrl->t;
+        w = (t + 1.0) / (t + 2.0);
+        wa = 1.0 / (t + 2.0);
+        th = ctrl->theta;
+        halpern = ctrl->use_halpern;
+        unb = ctrl->has_unbounded_x;
+    }
+    __device__ void row(long long i, double xti, double xi, double (&a)[3]) const
+    {
+        const double dxi = xti - xi;
+        a[0] += dxi * dxi;
+        x[i] = halpern ? w * ((1.0 + th) * xti - th * xi) + wa * xa[i] : xti;
+        if (store && unb) {
+            const double di = projRec(dxi, lv[i], uv[i]);
+            d[i] = di;
+            a[1] = rcomb(R_MAX, a[1], fabs(di));
+            a[2] += c[i] * di;
+        }
+    }
+    // movement, certificate pieces and the inner-tolerance update (Section
+    // 3.3); the iteration counters advance after the dual step
+    __device__ void finalize(Ctrl* C, const double* t) const
+    {
+        C->ndx2 = t[0];
+        if (store) {
+            C->d_max = unb ? t[1] : 0.0;
+            C->cd = unb ? t[2] : 0.0;
+        }
+        if (C->eps_fixed <= 0.0)
+            C->eps = fmin(C->eps, fmax(C->gamma_inner * C->omega * sqrt(t[0]) / C->tau, C->eps_min));
+    }
+};
+
 // primal step, diagonal Q (Section 2.2 closed form), fused into A'y:
 //   x_T = clip((x/tau - c - A'y) / (q + 1/tau), l_v, u_v)
 struct EpiProx : EpiBase {
     static constexpr bool BULK = true;
-    static constexpr int NR = 0;
-    const double *y, *x, *c, *qd, *lv, *uv;
-    double *xt, *xbar;
+    static constexpr int NR = 3;
+    const double *y, *c, *qd, *lv, *uv;
+    double *x, *xt, *xbar;
+    HalpernX hx;
     // mixed precision: A' y = A' y_ref + A'(y - y_ref) (dy32, aty_ref), and
     // x_bar - x_ref is written for the dual step's product
     const float* dy32 = nullptr;
     const double *atyref = nullptr, *xref = nullptr;
     float* dxb32 = nullptr;
     double it;
-    __device__ void init() { it = ctrl->inv_tau; }
+    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
+    __device__ void init()
+    {
+        it = ctrl->inv_tau;
+        hx.init(ctrl);
+    }
     __device__ double xval(int j) const { return y[j]; }
     __device__ bool use32() const { return dy32 != nullptr; }
     __device__ float xval32(int j) const { return dy32[j]; }
     __device__ double rowref(int i) const { return atyref[i]; }
-    __device__ void row(int i, double s, Acc<NR>) const
+    __device__ void row(int i, double s, Acc<NR> a) const
     {
         const double xi = x[i];
         const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
@@ -340,22 +391,31 @@ struct EpiProx : EpiBase {
         const double xb = 2.0 * v - xi;
         xbar[i] = xb;
         if (dxb32) dxb32[i] = (float)(xb - xref[i]);
+        hx.row(i, v, xi, a);
     }
+    __device__ void finalize(const double* t) const { hx.finalize(ctrl, t); }
 };
 
-// extrapolated point x_bar = 2 x_T - x (eq. extrapolation)
+// extrapolated point x_bar = 2 x_T - x (eq. extrapolation) and the Halpern
+// average of x
 struct EpiXbar : EpiBase {
-    static constexpr int NR = 0;
-    const double *xt, *x;
+    static constexpr int NR = 3;
+    const double* xt;
     double* xbar;
+    HalpernX hx;
     const double* xref = nullptr;   // mixed precision: also x_bar - x_ref in FP32
     float* dxb32 = nullptr;
-    __device__ void elem(long long i, Acc<NR>) const
+    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
+    __device__ void init() { hx.init(ctrl); }
+    __device__ void elem(long long i, Acc<NR> a) const
     {
-        const double xb = 2.0 * xt[i] - x[i];
+        const double xti = xt[i], xi = hx.x[i];
+        const double xb = 2.0 * xti - xi;
         xbar[i] = xb;
         if (dxb32) dxb32[i] = (float)(xb - xref[i]);
+        hx.row(i, xti, xi, a);
     }
+    __device__ void finalize(const double* t) const { hx.finalize(ctrl, t); }
 };
 
 // x <- clip(x, l_v, u_v)
@@ -650,62 +710,20 @@ struct EpiDual : EpiBase {
             a[3] += supp_abs(yy, l, u);
         }
     }
-    __device__ void finalize(const double* t) const
-    {
-        ctrl->ndy2 = t[0];
-        if (store) {
-            ctrl->ytil_max = t[1];
-            ctrl->ptil_sum = t[2];
-            ctrl->ptil_abs = t[3];
-        }
-    }
-};
-
-// Halpern average of x, movement norm, inner-tolerance update (Section 3.3)
-// and the iteration counters
-struct EpiHalpX : EpiBase {
-    static constexpr int NR = 3;
-    const double *xt, *xa, *c, *lv, *uv;
-    double *x, *d;
-    int store;
-    double w, wa, th;
-    int halpern, unb;
-    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
-    __device__ void init()
-    {
-        const double t = (double)ctrl->t;
-        w = (t + 1.0) / (t + 2.0);
-        wa = 1.0 / (t + 2.0);
-        th = ctrl->theta;
-        halpern = ctrl->use_halpern;
-        unb = ctrl->has_unbounded_x;
-    }
-    __device__ void elem(long long i, Acc<NR> a) const
-    {
-        const double xti = xt[i], xi = x[i];
-        const double dxi = xti - xi;
-        a[0] += dxi * dxi;
-        x[i] = halpern ? w * ((1.0 + th) * xti - th * xi) + wa * xa[i] : xti;
-        if (store && unb) {
-            const double di = projRec(dxi, lv[i], uv[i]);
-            d[i] = di;
-            a[1] = rcomb(R_MAX, a[1], fabs(di));
-            a[2] += c[i] * di;
-        }
-    }
+    // the last kernel of an iteration: the counters advance here, and the
+    // residual of the round's first step is kept for the restart test
     __device__ void finalize(const double* t) const
     {
         Ctrl* C = ctrl;
-        C->ndx2 = t[0];
+        C->ndy2 = t[0];
         if (store) {
-            C->d_max = unb ? t[1] : 0.0;
-            C->cd = unb ? t[2] : 0.0;
+            C->ytil_max = t[1];
+            C->ptil_sum = t[2];
+            C->ptil_abs = t[3];
         }
-        if (C->eps_fixed <= 0.0)
-            C->eps = fmin(C->eps, fmax(C->gamma_inner * C->omega * sqrt(t[0]) / C->tau, C->eps_min));
         C->k += 1;
         C->t += 1;
-        if (C->t == 1) C->R_start = sqrt(C->omega * t[0] + C->ndy2 / C->omega);
+        if (C->t == 1) C->R_start = sqrt(C->omega * C->ndx2 + C->ndy2 / C->omega);
     }
 };
 
@@ -1137,12 +1155,21 @@ hipError_t launch_init_start(const DevState& S, hipStream_t s)
     return run_vec(S, (long long)S.n + S.m, e, s);
 }
 
-hipError_t launch_prox_diag(const DevState& S, hipStream_t s)
+static HalpernX halpern_x(const DevState& S, int store_delta)
+{
+    HalpernX h{};
+    h.xa = S.xa; h.c = S.c; h.lv = S.lv; h.uv = S.uv; h.x = S.x; h.d = S.dx;
+    h.store = store_delta;
+    return h;
+}
+
+hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s)
 {
     EpiProx e{};
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.qd = S.qd; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt;
     e.xbar = S.xbar;
+    e.hx = halpern_x(S, store_delta);
     if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; e.xref = S.xref; e.dxb32 = S.dxb32; }
     return run_spmv(S, S.AT, e, s);
 }
@@ -1227,11 +1254,12 @@ hipError_t launch_update(const DevState& S, long long seq, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_xbar(const DevState& S, hipStream_t s)
+hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s)
 {
     EpiXbar e{};
     e.ctrl = S.ctrl;
-    e.xt = S.xt; e.x = S.x; e.xbar = S.xbar;
+    e.xt = S.xt; e.xbar = S.xbar;
+    e.hx = halpern_x(S, store_delta);
     if (S.mixed) { e.xref = S.xref; e.dxb32 = S.dxb32; }
     return run_vec(S, S.n, e, s);
 }
@@ -1252,15 +1280,6 @@ hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s)
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
     if (S.mixed) { e.dxb32 = S.dxb32; e.axref = S.axref; e.yref = S.yref; e.dy32 = S.dy32; }
     return run_spmv(S, S.A, e, s);
-}
-
-hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s)
-{
-    EpiHalpX e{};
-    e.ctrl = S.ctrl;
-    e.xt = S.xt; e.xa = S.xa; e.c = S.c; e.lv = S.lv; e.uv = S.uv; e.x = S.x; e.d = S.dx;
-    e.store = store_delta;
-    return run_vec(S, S.n, e, s);
 }
 
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,

@@ -133,7 +133,8 @@ struct DevState {
 // ---- launchers (kernels.hip) ------------------------------------------------
 // Every launcher enqueues on `s` and returns hipGetLastError().
 hipError_t launch_init_start(const DevState& S, hipStream_t s);
-hipError_t launch_prox_diag(const DevState& S, hipStream_t s);
+// closed-form primal step fused with x_bar and the Halpern average of x
+hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
 // tail = R v for a factored Q (no-op otherwise); bulk: FP32 in mixed precision
@@ -144,10 +145,10 @@ hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_dir(const DevState& S, hipStream_t s);
 hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_update(const DevState& S, long long seq, hipStream_t s);
-hipError_t launch_xbar(const DevState& S, hipStream_t s);          // x_bar = 2 x_T - x
+// x_bar = 2 x_T - x fused with the Halpern average of x
+hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- proj_X(x)
 hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s);
-hipError_t launch_halpx(const DevState& S, int store_delta, hipStream_t s);
 // KKT pieces at (x, y); with `full` also the infeasibility certificates
 // (and, with `dinf`, the unboundedness ones) and the solver's decision
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
