@@ -164,13 +164,14 @@ def main_batch(args, torch, P, I):
 def portfolio_bytes(q, fam, vb):
     """Algorithmic bytes of one launch of the diagonal-Q path's two products
     (vb = bytes per nonzero: 12 in FP64, 8 with FP32 values and int32
-    columns).  rhs: A'y fused with the closed-form primal step -- the
-    nonzeros, row pointers, y gathered once, x, c, q, l_v, u_v read, x_T and
-    x_bar written.  dual: A x_bar fused with the dual step and Halpern on y --
-    the nonzeros, row pointers, x_bar gathered once, y, y anchor, l_c, u_c
-    read, y_T and y written."""
+    columns).  rhs: A'y fused with the closed-form primal step, x_bar and the
+    Halpern average of x -- the nonzeros, row pointers, y gathered once, x,
+    c, q, l_v, u_v and the x anchor read, x_T, x_bar and x written.  dual:
+    A x_bar fused with the dual step and Halpern on y -- the nonzeros, row
+    pointers, x_bar gathered once, y, y anchor, l_c, u_c read, y_T and y
+    written."""
     if fam == "rhs":
-        return vb * q.nnz_A + 4 * (q.n + 1) + 8 * q.m + 8 * q.n * 7
+        return vb * q.nnz_A + 4 * (q.n + 1) + 8 * q.m + 8 * q.n * 9
     return vb * q.nnz_A + 4 * (q.m + 1) + 8 * q.n + 8 * q.m * 6
 
 
@@ -265,7 +266,8 @@ def main_serve(args, torch, P, I):
     mixed = args.precision == "mixed"
     params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter,
                                  precision=P.PRECISION_MIXED if mixed else P.PRECISION_FP64)
-    cfg = dict(batch_lanes=args.lanes, single_workers=args.workers, batch_max_dim=args.batch_max_dim,
+    cfg = dict(batch_lanes=args.lanes, general_lanes=args.general_lanes, single_workers=args.workers,
+               batch_max_dim=args.batch_max_dim, general_max_dim=args.general_max_dim,
                batch_linger_us=args.linger_us)
     with P.Server(params, **cfg) as srv:
         for q in (I.mpc(0), I.random_small(0, n=2000), I.portfolio(0, n_assets=10000, k_factors=50)):
@@ -354,9 +356,11 @@ def main():
                     default="large_sparse")
     ap.add_argument("--requests", type=int, default=1000, help="requests of the served stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="arrivals per second of the served stream")
-    ap.add_argument("--lanes", type=int, default=4)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--lanes", type=int, default=2, help="server lanes for diagonal-Q requests")
+    ap.add_argument("--general-lanes", type=int, default=2, help="server lanes for non-diagonal-Q requests")
+    ap.add_argument("--workers", type=int, default=8, help="server single-path workers")
     ap.add_argument("--batch-max-dim", type=int, default=20000)
+    ap.add_argument("--general-max-dim", type=int, default=3000)
     ap.add_argument("--linger-us", type=float, default=200.0)
     ap.add_argument("--one-at-a-time-s", type=float, default=20.0,
                     help="seconds spent solving the served stream one request at a time (FP64)")

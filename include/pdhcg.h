@@ -272,11 +272,13 @@ void qp_batch_destroy(qp_batch* bt);
 /* ---- request server: continuous batching ---------------------------------
  *
  * A server takes QPs of any size as they arrive and solves them on one GPU:
- * requests with n + m <= batch_max_dim and no row of A, A' or Q longer than
- * QP_BATCH_MAX_ROW nonzeros are gathered into batched launches (one workgroup per
- * instance, as qp_batch_solve), the others are solved on
+ * requests with n + m <= batch_max_dim (general_max_dim for a non-diagonal Q)
+ * and no row of A, A' or Q longer than QP_BATCH_MAX_ROW nonzeros are gathered
+ * into batched launches (one workgroup per instance, as qp_batch_solve; a
+ * launch ends with its slowest instance, so diagonal-Q and non-diagonal-Q
+ * requests have lanes of their own), the others are solved on
  * the single-problem path by worker threads, each on its own stream.  Up to
- * `batch_lanes` batched launches and `single_workers` single solves are in
+ * `batch_lanes + general_lanes` batched launches and `single_workers` single solves are in
  * flight at once; a request is admitted when a lane or worker is free and
  * the device bytes of everything in flight plus its own (its CSR data and
  * solver state) stay within `device_budget`.  Requests that arrive while
@@ -289,11 +291,14 @@ typedef struct qp_server qp_server;
 
 typedef struct {
     int64_t device_budget;    /* bytes of device memory for requests in flight; 8 GiB */
-    int64_t batch_max_dim;    /* n + m at or below which a request joins a batch; 20000 */
-    int32_t batch_lanes;      /* batched launches in flight; 4 */
-    int32_t single_workers;   /* single-path solves in flight; 4 */
+    int64_t batch_max_dim;    /* diagonal or zero Q: n + m at or below which a request
+                                 joins a batch; 20000 */
+    int64_t general_max_dim;  /* non-diagonal Q (inner solve in the workgroup): the same
+                                 limit; 3000 */
+    int32_t batch_lanes;      /* batched launches in flight for diagonal-Q requests; 2 */
+    int32_t general_lanes;    /* batched launches in flight for non-diagonal-Q requests; 2 */
+    int32_t single_workers;   /* single-path solves in flight; 8 */
     int32_t max_batch;        /* instances per batched launch; 1024 */
-    int32_t reserved;
     double batch_linger_us;   /* a free lane waits up to this long (from the oldest waiting
                                  request's arrival) for more requests before launching; 200 */
 } qp_server_config;

@@ -68,8 +68,9 @@ class QPInfo(C.Structure):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("device_budget", _i64), ("batch_max_dim", _i64), ("batch_lanes", C.c_int32),
-                ("single_workers", C.c_int32), ("max_batch", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("device_budget", _i64), ("batch_max_dim", _i64), ("general_max_dim", _i64),
+                ("batch_lanes", C.c_int32), ("general_lanes", C.c_int32),
+                ("single_workers", C.c_int32), ("max_batch", C.c_int32),
                 ("batch_linger_us", C.c_double)]
 
 

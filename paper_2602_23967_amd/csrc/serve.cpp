@@ -4,9 +4,13 @@
 // stream on which at most one batched launch (one workgroup per instance)
 // runs; when a lane's launch completes, the scheduler copies its results out
 // and gives the lane the requests that arrived meanwhile, so new work starts
-// while the other lanes' launches are still running.  Requests too large
-// for one workgroup go to worker threads that solve them one at a time on
-// the single-problem path (each handle has its own stream).  Admission is by
+// while the other lanes' launches are still running.  A launch ends with its
+// slowest instance, so lanes come in two classes: instances with the
+// closed-form primal step (diagonal or zero Q, a few microseconds per
+// iteration) and instances with an inner solve (non-diagonal Q), each with
+// its own queue, so fast requests never wait behind slow ones.  Requests too
+// large for one workgroup go to worker threads that solve them one at a time
+// on the single-problem path (each handle has its own stream).  Admission is by
 // device bytes: a request starts only when the bytes of everything in flight
 // plus its own stay within the budget; the waiting queue is first come,
 // first served within each route.
@@ -38,7 +42,8 @@ struct Request {
     std::vector<double> qv, av, c, b, lb, ub;
     std::vector<char> sense;
     size_t bytes = 0;
-    int route = 0;
+    int route = 0;   // 0 batched, 1 single path
+    int klass = 0;   // batched class: 0 closed form, 1 inner solve
     double t_submit = 0.0;
     // outcome
     int state = 0;   // 0 waiting, 1 running, 2 finished
@@ -67,6 +72,7 @@ size_t footprint(const Request& r, int route)
 }
 
 struct Lane {
+    int klass = 0;
     hipStream_t stream = nullptr;
     qp_batch* bt = nullptr;
     std::vector<Request*> reqs;
@@ -83,7 +89,7 @@ struct qp_server {
     double t0 = 0.0;
     std::mutex mu;
     std::condition_variable cv_sched, cv_work, cv_done;
-    std::deque<Request*> bq, sq;   // waiting, per route
+    std::deque<Request*> bq[2], sq;   // waiting: per batched class, single path
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     int64_t next_id = 0;
     size_t in_flight = 0;
@@ -220,21 +226,23 @@ void scheduler(qp_server* s)
         double wake = -1.0;   // > 0: seconds until the oldest request's linger ends
         if (!s->stop) {
             for (Lane& L : s->lanes) {
-                if (L.bt || s->bq.empty()) continue;
-                const double age = now_s() - s->bq.front()->t_submit;
-                if ((int64_t)s->bq.size() < s->cfg.max_batch && age < linger) {
-                    wake = linger - age;
-                    break;
+                std::deque<Request*>& q = s->bq[L.klass];
+                if (L.bt || q.empty()) continue;
+                const double age = now_s() - q.front()->t_submit;
+                if ((int64_t)q.size() < s->cfg.max_batch && age < linger) {
+                    const double wl = linger - age;
+                    wake = wake > 0.0 ? std::min(wake, wl) : wl;
+                    continue;
                 }
                 size_t bytes = 0;
-                while (!s->bq.empty() && (int64_t)L.reqs.size() < s->cfg.max_batch) {
-                    Request* r = s->bq.front();
+                while (!q.empty() && (int64_t)L.reqs.size() < s->cfg.max_batch) {
+                    Request* r = q.front();
                     if (s->in_flight + bytes + r->bytes > (size_t)s->cfg.device_budget) break;
-                    s->bq.pop_front();
+                    q.pop_front();
                     L.reqs.push_back(r);
                     bytes += r->bytes;
                 }
-                if (L.reqs.empty()) break;   // budget full: wait for completions
+                if (L.reqs.empty()) continue;   // budget full: wait for completions
                 s->in_flight += bytes;
                 L.bytes = bytes;
                 const double t = rel(s);
@@ -317,10 +325,11 @@ qp_server_config qp_server_config_default(void)
     qp_server_config c{};
     c.device_budget = (int64_t)8 << 30;
     c.batch_max_dim = 20000;
-    c.batch_lanes = 4;
-    c.single_workers = 4;
+    c.general_max_dim = 3000;
+    c.batch_lanes = 2;
+    c.general_lanes = 2;
+    c.single_workers = 8;
     c.max_batch = 1024;
-    c.reserved = 0;
     c.batch_linger_us = 200.0;
     return c;
 }
@@ -331,8 +340,9 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
     *out = nullptr;
     const qp_server_config c = cfg ? *cfg : qp_server_config_default();
     const qp_params p = params ? *params : qp_params_default();
-    if (c.device_budget <= 0 || c.batch_max_dim < 0 || c.batch_lanes < 0 || c.single_workers < 0 ||
-        c.batch_lanes + c.single_workers < 1 || c.max_batch < 1 || !(c.batch_linger_us >= 0.0))
+    if (c.device_budget <= 0 || c.batch_max_dim < 0 || c.general_max_dim < 0 || c.batch_lanes < 0 ||
+        c.general_lanes < 0 || c.single_workers < 0 || c.batch_lanes + c.general_lanes + c.single_workers < 1 ||
+        c.max_batch < 1 || !(c.batch_linger_us >= 0.0))
         return fail(QP_ERR_INVALID_ARG, "invalid server configuration");
     if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 ||
         (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))
@@ -348,7 +358,8 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
         delete s;
         return fail(QP_ERR_DEVICE, "hipGetDevice failed");
     }
-    s->lanes.resize((size_t)c.batch_lanes);
+    s->lanes.resize((size_t)(c.batch_lanes + c.general_lanes));
+    for (int i = 0; i < c.batch_lanes + c.general_lanes; ++i) s->lanes[i].klass = i < c.batch_lanes ? 0 : 1;
     for (Lane& L : s->lanes) {
         if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess) {
             for (Lane& K : s->lanes)
@@ -357,7 +368,7 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
             return fail(QP_ERR_DEVICE, "hipStreamCreate failed");
         }
     }
-    if (c.batch_lanes > 0) s->sched = std::thread(scheduler, s);
+    if (c.batch_lanes + c.general_lanes > 0) s->sched = std::thread(scheduler, s);
     for (int i = 0; i < c.single_workers; ++i) s->workers.emplace_back(worker, s);
     *out = s;
     return 0;
@@ -428,8 +439,18 @@ int64_t qp_server_submit(qp_server* s, int64_t n, int64_t m,
         for (int64_t e = 0; e < Ap[m]; ++e) ++colcnt[Aj[e]];
         for (int64_t i = 0; i < n; ++i) longest = std::max(longest, colcnt[i]);
     }
-    const bool small = n + m <= s->cfg.batch_max_dim && longest <= QP_BATCH_MAX_ROW;
-    r->route = (s->cfg.batch_lanes > 0 && (small || s->cfg.single_workers == 0)) ? 0 : 1;
+    bool diagonal = true;
+    if (Qp)
+        for (int64_t i = 0; i < n && diagonal; ++i)
+            for (int64_t e = Qp[i]; e < Qp[i + 1]; ++e)
+                if (Qj[e] != i) { diagonal = false; break; }
+    r->klass = diagonal ? 0 : 1;
+    const int64_t lanes = diagonal ? s->cfg.batch_lanes : s->cfg.general_lanes;
+    const int64_t limit = diagonal ? s->cfg.batch_max_dim : s->cfg.general_max_dim;
+    const bool small = n + m <= limit && longest <= QP_BATCH_MAX_ROW;
+    if (lanes > 0 && (small || s->cfg.single_workers == 0)) r->route = 0;
+    else if (s->cfg.single_workers > 0) r->route = 1;
+    else return fail(QP_ERR_INVALID_ARG, "no lane or worker takes this request");
     r->bytes = footprint(*r, r->route);
     if (r->bytes > (size_t)s->cfg.device_budget) return fail(QP_ERR_INVALID_ARG, "request exceeds the device budget");
     r->t_submit = t_submit;
@@ -441,7 +462,7 @@ int64_t qp_server_submit(qp_server* s, int64_t n, int64_t m,
     raw->times.submitted = t_submit - s->t0;
     s->reqs.emplace(raw->id, std::move(r));
     if (raw->route == 0) {
-        s->bq.push_back(raw);
+        s->bq[raw->klass].push_back(raw);
         s->cv_sched.notify_one();
     } else {
         s->sq.push_back(raw);
@@ -490,7 +511,8 @@ void qp_server_destroy(qp_server* s)
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->stop = true;
-        s->bq.clear();
+        s->bq[0].clear();
+        s->bq[1].clear();
         s->sq.clear();
     }
     s->cv_sched.notify_all();

@@ -187,7 +187,7 @@ def test_server_config_and_validation():
     import ctypes as C
     L = P.lib()
     h = C.c_void_p()
-    bad = P.qp_server_config_default(batch_lanes=0, single_workers=0)
+    bad = P.qp_server_config_default(batch_lanes=0, general_lanes=0, single_workers=0)
     assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
     bad = P.qp_server_config_default(max_batch=0)
     assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
