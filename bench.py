@@ -289,8 +289,7 @@ def main_serve(args, torch, P, I):
         for i, rid in enumerate(ids):
             srv.wait(rid)
             res.append(srv.result(rid))
-            if (i + 1) % 100 == 0:
-                log(f"{i + 1} requests done at {time.perf_counter() - t0:.1f}s")
+            log(f"request {i + 1}/{len(ids)} ({kinds[i]}, n={qs[i].n}) done at {time.perf_counter() - t0:.1f}s")
         elapsed = time.perf_counter() - t0
     lat = np.array([tm["finished"] - tm["submitted"] for _, tm in res])
     first = min(tm["submitted"] for _, tm in res)

@@ -87,15 +87,8 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
-#if PDHCG_NT
-            // matrix entries are used once per product: stream them past the
-            // caches so the gathered operand part stays resident in L2
-            cj[i] = q < cnt ? __builtin_nontemporal_load(M.col + d.k0 + q) : -1;
-            av[i] = q < cnt ? __builtin_nontemporal_load(val + d.k0 + q) : T(0);
-#else
             cj[i] = q < cnt ? M.col[d.k0 + q] : -1;
             av[i] = q < cnt ? val[d.k0 + q] : T(0);
-#endif
         }
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {

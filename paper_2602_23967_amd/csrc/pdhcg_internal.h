@@ -8,7 +8,13 @@
 namespace pdhcg {
 
 constexpr int TPB = 256;        // threads per block for every kernel
-constexpr int NNZ_CAP = 2048;   // nonzeros staged in LDS per row block
+#ifndef PDHCG_NNZ_CAP
+#define PDHCG_NNZ_CAP 2048
+#endif
+#ifndef PDHCG_PART_ROWS_CAP
+#define PDHCG_PART_ROWS_CAP 1024
+#endif
+constexpr int NNZ_CAP = PDHCG_NNZ_CAP;   // nonzeros staged in LDS per row block
 constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at most)
 constexpr int VEC_GRID_MAX = 2048;
 // XCD-aware column partitioning: an operand larger than PART_MIN_COLS
@@ -21,11 +27,8 @@ constexpr int VEC_GRID_MAX = 2048;
 #define PDHCG_NPARTS 4
 #endif
 constexpr int NPARTS = PDHCG_NPARTS;
-#ifndef PDHCG_NT
-#define PDHCG_NT 0
-#endif
 constexpr int PART_MIN_COLS = 262144;
-constexpr int PART_ROWS_CAP = 1024;   // rows per block of a column part
+constexpr int PART_ROWS_CAP = PDHCG_PART_ROWS_CAP;   // rows per block of a column part
 constexpr int FIN_T = 1024;     // threads of the one-block finishing kernels
 
 // One work item of the row-block SpMV schedule.
