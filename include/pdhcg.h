@@ -85,6 +85,10 @@ typedef struct {
     double mprgp_abar_scale;  /* expansion step = scale / (||Q||_2 + 1/tau); 1.9 */
     int timing;               /* > 0: time every `timing`-th launch of each kernel family */
     int precision;            /* QP_PRECISION_FP64 (0, default) or QP_PRECISION_MIXED (1) */
+    int graph_steps;          /* > 0: the inner solve's steps are launched as a captured HIP
+                                 graph of this many steps (0: one launch per kernel; timing
+                                 forces 0); results are the same either way; 2 */
+    int reserved;
 } qp_params;
 
 /* Arithmetic of a solve.  FP64: every step in double precision.  MIXED: the

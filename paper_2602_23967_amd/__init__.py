@@ -45,7 +45,8 @@ class QPParams(C.Structure):
                 ("eps_inf", C.c_double), ("eta_scale", C.c_double), ("norm_safety", C.c_double),
                 ("power_tol", C.c_double), ("power_max_iter", _i64),
                 ("mprgp_gamma", C.c_double), ("mprgp_abar_scale", C.c_double),
-                ("timing", C.c_int), ("precision", C.c_int)]
+                ("timing", C.c_int), ("precision", C.c_int), ("graph_steps", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class QPInfo(C.Structure):

@@ -263,6 +263,10 @@ struct qp_handle {
     int64_t fam_launches[QP_NFAM] = {};
     // FP32 copies of the matrix values, made at the first mixed-precision solve
     float *val32_A = nullptr, *val32_AT = nullptr, *val32_Q = nullptr, *val32_R = nullptr;
+    // graph of `graph_steps` inner steps (captured once per precision)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0, graph_mixed = -1;
 };
 
 namespace {
@@ -677,7 +681,39 @@ void setup_ctrl(qp_handle* h, const qp_params& p, Ctrl& c)
 // status it has seen, so the GPU never waits for the host.
 // `exact`: form rhs (already done by the caller) and the gradient with a
 // product with Q; otherwise update both from the previous subproblem.
-int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact)
+// K inner steps (direction, H p, update) as one graph: the steps take no
+// per-step argument, so the same graph serves every subproblem of the handle
+int ensure_inner_graph(qp_handle* h, int K)
+{
+    DevState& S = h->S;
+    if (h->graph_exec && h->graph_steps == K && h->graph_mixed == S.mixed) return 0;
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    hipStream_t cs = h->own;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < K && err == hipSuccess; ++k) {
+        err = launch_dir(S, cs);
+        if (err == hipSuccess) err = launch_hp(S, cs);
+        if (err == hipSuccess) err = launch_update(S, cs);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(QP_ERR_DEVICE, std::string("graph capture failed: ") +
+                                       hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    h->graph = g;
+    HIPCHK(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+    h->graph_steps = K;
+    h->graph_mixed = S.mixed;
+    return 0;
+}
+
+int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact, int K)
 {
     DevState& S = h->S;
     hipStream_t s = h->stream;
@@ -691,8 +727,9 @@ int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact)
     }
     volatile unsigned long long* word = h->hstat;
     long long issued = 0;
+    const int batch = K > 0 ? K : 1;   // inner steps per launch (graph or eager)
     for (;;) {
-        const long long target = issued - lag;
+        const long long target = issued - (long long)lag * batch;
         if (target >= 0) {
             long long spins = 0;
             for (;;) {
@@ -714,6 +751,14 @@ int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact)
         }
         const unsigned long long w = *word;
         if ((long long)(w >> 1) >= base && (w & 1ull)) break;
+        if (K > 0) {
+            HIPCHK(hipGraphLaunch(h->graph_exec, s));
+            issued += K;
+            h->fam_launches[QP_FAM_DIR] += K;
+            h->fam_launches[QP_FAM_SPMV_HP] += K;
+            h->fam_launches[QP_FAM_UPDATE] += K;
+            continue;
+        }
         ++issued;
         {
             Timed t(h, QP_FAM_DIR);
@@ -721,11 +766,11 @@ int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact)
         }
         {
             Timed t(h, QP_FAM_SPMV_HP);
-            HIPCHK(launch_hp(S, base + issued, s));
+            HIPCHK(launch_hp(S, s));
         }
         {
             Timed t(h, QP_FAM_UPDATE);
-            HIPCHK(launch_update(S, base + issued, s));
+            HIPCHK(launch_update(S, s));
         }
     }
     gseq = base + issued + 1;
@@ -768,6 +813,9 @@ qp_params qp_params_default(void)
     p.mprgp_gamma = 1.0;
     p.mprgp_abar_scale = 1.9;
     p.timing = 0;
+    p.precision = QP_PRECISION_FP64;
+    p.graph_steps = 2;
+    p.reserved = 0;
     return p;
 }
 
@@ -862,6 +910,8 @@ void qp_destroy(qp_handle* h)
         (void)hipEventDestroy(e.ev[0]);
         (void)hipEventDestroy(e.ev[1]);
     }
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     if (h->hstat) (void)hipHostFree(h->hstat);
     if (h->own) (void)hipStreamDestroy(h->own);
     delete h;
@@ -880,12 +930,17 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     if (!h) return fail(QP_ERR_INVALID_ARG, "handle is NULL");
     const qp_params p = params ? *params : qp_params_default();
     if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 || p.max_inner < 0 || p.inner_lag < 0 ||
-        (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))
+        (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED) || p.graph_steps < 0 ||
+        p.graph_steps > 64)
         return fail(QP_ERR_INVALID_ARG, "invalid parameters");
     DevState& S = h->S;
     hipStream_t s = h->stream;
     const double t0 = now_s();
     if (int rc = set_precision(h, p.precision)) return rc;
+    // inner steps per graph launch (eager launches when timing kernel families)
+    const int K = (p.timing > 0 || S.qdiag) ? 0 : p.graph_steps;
+    if (K > 0)
+        if (int rc = ensure_inner_graph(h, K)) return rc;
 
     h->timing = p.timing;
     std::fill(h->fam_launches, h->fam_launches + QP_NFAM, 0);
@@ -945,7 +1000,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                 Timed t(h, QP_FAM_RHS);
                 HIPCHK(launch_rhs(S, s));
             }
-            int rc = inner_solve(h, gseq, p.inner_lag, exact);
+            int rc = inner_solve(h, gseq, p.inner_lag, exact, K);
             if (rc) return rc;
             Timed t(h, QP_FAM_HALPX);
             HIPCHK(launch_xbar(S, next_check, s));
@@ -1075,7 +1130,7 @@ int qp_subproblem(qp_handle* h, double tau, const double* rhs, double* x, double
     HIPCHK(hipStreamSynchronize(s));
     h->hstat[0] = 0;
     long long gseq = 1;
-    int rc = inner_solve(h, gseq, 2, true);
+    int rc = inner_solve(h, gseq, 2, true, 0);
     if (rc) return rc;
     HIPCHK(hipMemcpyAsync(x, S.xt, sizeof(double) * h->n, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));

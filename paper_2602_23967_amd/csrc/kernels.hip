@@ -195,7 +195,12 @@ __global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
     }
 }
 
-// one block: completes the long rows (segment sums in segment order), sums
+// long rows up to which the finishing kernel completes each row with the
+// whole block (beyond: one thread per row)
+constexpr int LR_COOP = 32;
+
+// one block: completes the long rows (their segment partials summed by a
+// fixed tree, or in segment order when there are many long rows), sums
 // the per-block partials in block order, and runs the epilogue's finalize
 template <class E>
 __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const double* partials)
@@ -208,12 +213,29 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
     double acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
-    for (int lr = threadIdx.x; lr < M.nlr; lr += FIN_T) {
-        const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
-        double total = 0.0;
-        for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
-        if (e.use32()) total += e.rowref(row);
-        e.row(row, total, acc);
+    if (M.nlr <= LR_COOP) {
+        // few long rows (a budget row, a dense column): the whole block sums
+        // each one's segment partials (fixed tree order)
+        __shared__ double lds1[FIN_T / 64];
+        for (int lr = 0; lr < M.nlr; ++lr) {
+            const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
+            double part[1] = {0.0};
+            for (int i = threadIdx.x; i < nseg; i += FIN_T) part[0] += M.seg_part[base + i];
+            block_reduce<SumOne, FIN_T>(part, lds1);
+            if (threadIdx.x == 0) {
+                double total = part[0];
+                if (e.use32()) total += e.rowref(row);
+                e.row(row, total, acc);
+            }
+        }
+    } else {
+        for (int lr = threadIdx.x; lr < M.nlr; lr += FIN_T) {
+            const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
+            double total = 0.0;
+            for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
+            if (e.use32()) total += e.rowref(row);
+            e.row(row, total, acc);
+        }
     }
     if constexpr (E::NR > 0) {
 #pragma unroll 4
@@ -480,6 +502,8 @@ struct EpiRhsGrad : EpiBase {
         c->need_g = 0;
         c->skip_update = 0;
         c->g_inv_tau = c->inv_tau;
+        c->seq_base = seq;
+        c->step = 0;
         inner_decide(c, t[0], t[1], t[2], seq, dstat);
     }
 };
@@ -515,6 +539,8 @@ struct EpiGinit : EpiBase {
         c->skip_update = 0;
         c->g_inv_tau = c->inv_tau;
         if (isinf(c->eps) && c->eps_fixed <= 0.0) c->eps = fmax(c->gamma_inner * sqrt(t[0]), c->eps_min);
+        c->seq_base = seq;
+        c->step = 0;
         inner_decide(c, t[0], t[1], t[2], seq, dstat);
     }
 };
@@ -527,7 +553,6 @@ struct EpiStepA : EpiBase {
     const double *p, *lv, *uv, *rhs;
     double *xt, *g, *hp;
     unsigned long long* dstat;
-    long long seq;
     double it, abar;
     int ng;
     int mixed = 0;   // mixed precision: H p in FP32; the gradient after an expansion stays FP64
@@ -563,6 +588,8 @@ struct EpiStepA : EpiBase {
     {
         Ctrl* c = ctrl;
         c->hp_active += 1;
+        c->step += 1;   // every inner step that is not past the stop runs this
+        const long long seq = c->seq_base + c->step;
         if (ng) {
             c->need_g = 0;
             c->skip_update = 1;
@@ -600,7 +627,6 @@ struct EpiStepB : EpiBase {
     const double *p, *hp, *lv, *uv;
     double *xt, *g;
     unsigned long long* dstat;
-    long long seq;
     double alpha, abar;
     int kindstep;
     __device__ bool skip() const { return ctrl->done != 0 || ctrl->skip_update != 0; }
@@ -627,6 +653,7 @@ struct EpiStepB : EpiBase {
         Ctrl* c = ctrl;
         c->inner_it += 1;
         c->inner_total += 1;
+        const long long seq = c->seq_base + c->step;
         if (kindstep == STEP_EXPAND) {
             c->last_step = STEP_EXPAND;
             c->need_g = 1;
@@ -1222,7 +1249,7 @@ hipError_t launch_dir(const DevState& S, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s)
+hipError_t launch_hp(const DevState& S, hipStream_t s)
 {
     if (S.R.rows) {
         EpiTailHp t{};
@@ -1234,16 +1261,16 @@ hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s)
     EpiStepA e{};
     e.ctrl = S.ctrl;
     e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
-    e.dstat = S.dstat; e.seq = seq; e.mixed = S.mixed;
+    e.dstat = S.dstat; e.mixed = S.mixed;
     return run_spmv(S, S.Q, e, s);
 }
 
-hipError_t launch_update(const DevState& S, long long seq, hipStream_t s)
+hipError_t launch_update(const DevState& S, hipStream_t s)
 {
     EpiStepB e{};
     e.ctrl = S.ctrl;
     e.p = S.p; e.hp = S.hp; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt; e.g = S.g;
-    e.dstat = S.dstat; e.seq = seq;
+    e.dstat = S.dstat;
     return run_vec(S, S.n, e, s);
 }
 

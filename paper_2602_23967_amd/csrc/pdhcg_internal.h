@@ -80,6 +80,10 @@ struct Ctrl {
     double gp2, b2, ptp;           // ||g^P||^2, ||beta||^2, phit'phi at the current x
     double res;                    // ||g^P|| at the last decision
     long long inner_it, inner_total, max_inner;
+    // status sequence of the inner solve: the subproblem's base number (from
+    // the host) and the inner steps that ran; step i posts seq_base + i, so
+    // the inner-step kernels take no per-step argument (graph-capturable)
+    long long seq_base, step;
     long long hp_active;           // launches of the inner product that did the product
     int done, need_g, skip_update, dir_mode, last_step, step_kind, proportional, pad0;
     // outer state (Sections 3.1-3.2)
@@ -146,8 +150,8 @@ hipError_t launch_tail(const DevState& S, const double* v, double* tail, bool bu
 // gradient (no product with Q); starts the inner solve like launch_ginit
 hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_dir(const DevState& S, hipStream_t s);
-hipError_t launch_hp(const DevState& S, long long seq, hipStream_t s);
-hipError_t launch_update(const DevState& S, long long seq, hipStream_t s);
+hipError_t launch_hp(const DevState& S, hipStream_t s);
+hipError_t launch_update(const DevState& S, hipStream_t s);
 // x_bar = 2 x_T - x fused with the Halpern average of x
 hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- proj_X(x)

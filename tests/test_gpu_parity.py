@@ -366,3 +366,21 @@ def test_large_infeasible_variant(torch):
     r1, r2 = q.meta["rows"]
     top = set(np.argsort(-np.abs(g.y))[:2])
     assert top == {r1, r2} and g.y[r1] * g.y[r2] < 0
+
+
+@pytest.mark.parametrize("make", [lambda: I.random_small(0), lambda: I.mixed_bounds(0),
+                                  lambda: I.random_factored(1, n=600, m=200, k=30)])
+def test_graph_inner_steps_match_eager(torch, make):
+    """The inner steps launched as captured graphs (2 or 5 steps per graph,
+    replayed many times, eager launches in between) give the eager launches'
+    result bit for bit, in FP64 and in mixed precision, over repeated solves."""
+    q = make()
+    with P.Solver(q) as s:
+        for prec in (P.PRECISION_FP64, P.PRECISION_MIXED):
+            ref = s.solve(graph_steps=0, precision=prec)
+            for k in (2, 5, 2):
+                g = s.solve(graph_steps=k, precision=prec)
+                assert g.status == ref.status
+                assert g.info["iterations"] == ref.info["iterations"]
+                assert g.info["inner_iterations"] == ref.info["inner_iterations"]
+                assert np.array_equal(g.x, ref.x) and np.array_equal(g.y, ref.y)
