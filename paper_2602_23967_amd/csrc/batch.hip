@@ -117,7 +117,27 @@ __device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, co
 
 __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
                                 const double* mval, const int* trp, const int* tcol, const double* tval,
-                                double tol, long long max_iter, double* v, double* w, double* u, double* lds);
+                                double tol, long long max_iter, double* v, double* w, double* u, double* lds,
+                                double* sbuf);
+
+// The same product with the operand staged in the workgroup's LDS (sv[j -
+// off] holds the operand, or in mixed precision its difference from the
+// reference point): identical arithmetic, LDS gathers instead of L2 ones.
+template <bool F32>
+__device__ __forceinline__ double row_dot_lds(const int* rp, const int* col, const double* val,
+                                              const float* val32, const double* sv, int off, double ref,
+                                              int row)
+{
+    if constexpr (F32) {
+        float s = 0.0f;
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)sv[col[q] - off];
+        return ref + (double)s;
+    } else {
+        double s = 0.0;
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * sv[col[q] - off];
+        return s;
+    }
+}
 
 // the inner step's product H p: FP32 values, direction and sum in mixed
 // precision (the inner solve re-forms its gradient in FP64 at every
@@ -145,6 +165,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
                                                    double* u, double* out)
 {
     __shared__ double lds[2 * (TPB / 64)];
+    __shared__ double sbuf[BATCH_LDS];
     __shared__ int s_b;
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(queue, 1);
@@ -164,7 +185,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
         const int active = uniform_int((m > 0 && nnz > 0 && !skip) ? 1 : 0);
         double sig = 0.0;
         if (active) sig = power_norm_wg(c0, n, r0, m, mrp, mcol, mval, trp, tcol, tval, tol, max_iter, v, w,
-                                        u, lds);
+                                        u, lds, sbuf);
         if (threadIdx.x == 0) out[b] = sig;
         __syncthreads();
     }
@@ -174,8 +195,14 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
 // workgroup; every branch below is on workgroup-uniform values)
 __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
                                 const double* mval, const int* trp, const int* tcol, const double* tval,
-                                double tol, long long max_iter, double* v, double* w, double* u, double* lds)
+                                double tol, long long max_iter, double* v, double* w, double* u, double* lds,
+                                double* sbuf)
 {
+    // a small instance keeps v and w in LDS (the same values as the global
+    // copies, gathered from LDS)
+    const int stage = (n + m <= BATCH_LDS) ? 1 : 0;
+    double* sv = sbuf;
+    double* sw = sbuf + n;
     {
         // start vector: SplitMix64 of the local index (seed 0), in [-1, 1)
         double acc[1] = {0.0};
@@ -190,14 +217,20 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
         }
         wg_reduce<1, 0u>(acc, lds);
         const double nv = sqrt(acc[0]);
-        for (int j = threadIdx.x; j < n; j += TPB) v[c0 + j] /= nv;
+        for (int j = threadIdx.x; j < n; j += TPB) {
+            const double vj = v[c0 + j] / nv;
+            v[c0 + j] = vj;
+            if (stage) sv[j] = vj;
+        }
         __syncthreads();
         double sig = 0.0, prev = 0.0;
         for (long long it = 1; it <= max_iter; ++it) {
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < m; i += TPB) {
-                const double s = row_dot(mrp, mcol, mval, v, r0 + i);
+                const double s = stage ? row_dot_lds<false>(mrp, mcol, mval, nullptr, sv, c0, 0.0, r0 + i)
+                                       : row_dot(mrp, mcol, mval, v, r0 + i);
                 w[r0 + i] = s;
+                if (stage) sw[i] = s;
                 acc[0] += s * s;
             }
             wg_reduce<1, 0u>(acc, lds);
@@ -205,14 +238,19 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
             if (sig == 0.0) break;
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < n; i += TPB) {
-                const double s = row_dot(trp, tcol, tval, w, c0 + i);
+                const double s = stage ? row_dot_lds<false>(trp, tcol, tval, nullptr, sw, r0, 0.0, c0 + i)
+                                       : row_dot(trp, tcol, tval, w, c0 + i);
                 u[c0 + i] = s;
                 acc[0] += s * s;
             }
             wg_reduce<1, 0u>(acc, lds);
             const double nu = sqrt(acc[0]);
             if (nu == 0.0) break;
-            for (int i = threadIdx.x; i < n; i += TPB) v[c0 + i] = u[c0 + i] / nu;
+            for (int i = threadIdx.x; i < n; i += TPB) {
+                const double vi = u[c0 + i] / nu;
+                v[c0 + i] = vi;
+                if (stage) sv[i] = vi;
+            }
             __syncthreads();
             if (fabs(sig - prev) <= tol * sig) break;
             prev = sig;
@@ -224,7 +262,7 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
 // ---- the solve -----------------------------------------------------------------
 
 template <bool F32>
-__device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds)
+__device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds, double* sbuf)
 {
     // per-instance values in scalar registers: the branches on them (closed
     // form vs inner solve, certificates) must be seen as uniform, or the
@@ -258,9 +296,17 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         x[i] = v; xa[i] = v; xt[i] = v;
         if constexpr (F32) { xref[v0 + i] = 0.0; aty[i] = 0.0; }
     }
+    // a closed-form instance small enough keeps the operands of its two
+    // products in LDS: sx (x_bar, written by the primal step) and sy (y,
+    // written by the dual step), or their differences from the reference
+    // point in mixed precision
+    const int stage = (!qgen && n + m <= BATCH_LDS) ? 1 : 0;
+    double* sx = sbuf;
+    double* sy = sbuf + n;
     for (int j = tid; j < m; j += TPB) {
         y[j] = 0.0; ya[j] = 0.0; yt[r0 + j] = 0.0;
         if constexpr (F32) { yref[r0 + j] = 0.0; axref[j] = 0.0; }
+        if (stage) sy[j] = 0.0;
     }
     __syncthreads();
 
@@ -388,8 +434,15 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             if (restart) {
                 for (int i = tid; i < n; i += TPB) { x[i] = xt[i]; xa[i] = xt[i]; }
                 for (int j = tid; j < m; j += TPB) { y[j] = yt[r0 + j]; ya[j] = yt[r0 + j]; }
-                __syncthreads();
             }
+            if (stage) {
+                // y after a restart, and (mixed) its difference from the new reference
+                for (int j = tid; j < m; j += TPB) {
+                    if constexpr (F32) sy[j] = y[j] - yref[r0 + j];
+                    else sy[j] = y[j];
+                }
+            }
+            __syncthreads();
         }
         if (k >= P.max_iter) { status = 4; break; }
         const bool store = ((k + 1) % P.check_every == 0) || (k + 1 >= P.max_iter);
@@ -397,11 +450,18 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         if (!qgen) {
             // ---- primal step: closed form (Section 2.2) and x_bar -----------------
             for (int i = tid; i < n; i += TPB) {
-                const double s = row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
+                const double s =
+                    stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
+                          : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
                 const double xi = x[i];
                 const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
                 xt[i] = v;
-                xbar[v0 + i] = 2.0 * v - xi;
+                const double xb = 2.0 * v - xi;
+                xbar[v0 + i] = xb;
+                if (stage) {
+                    if constexpr (F32) sx[i] = xb - xref[v0 + i];
+                    else sx[i] = xb;
+                }
             }
             __syncthreads();
         } else {
@@ -503,14 +563,21 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         double a[7] = {0, 0, 0, 0, 0, 0, 0};
         constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
         for (int j = tid; j < m; j += TPB) {
-            const double s = row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j);
+            const double s =
+                stage ? row_dot_lds<F32>(B.arp, B.acol, B.aval, B.aval32, sx, v0, axref[j], r0 + j)
+                      : row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j);
             const double yj = y[j], l = lc[j], u = uc[j];
             const double v = yj / sigma + s;
             const double ytj = sigma * (v - clampd(v, l, u));
             const double dy = ytj - yj;
             a[1] += dy * dy;
             yt[r0 + j] = ytj;
-            y[j] = P.use_halpern ? w * ((1.0 + th) * ytj - th * yj) + wa * ya[j] : ytj;
+            const double yn = P.use_halpern ? w * ((1.0 + th) * ytj - th * yj) + wa * ya[j] : ytj;
+            y[j] = yn;
+            if (stage) {
+                if constexpr (F32) sy[j] = yn - yref[r0 + j];
+                else sy[j] = yn;
+            }
             if (store) {
                 const double yy = projY(dy, l, u);
                 ytil[r0 + j] = yy;
@@ -564,6 +631,7 @@ template <bool F32>
 __global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
 {
     __shared__ double lds[16 * (TPB / 64)];
+    __shared__ double sbuf[BATCH_LDS];
     __shared__ int s_b;
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
@@ -571,7 +639,7 @@ __global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
         const int b = uniform_int(s_b);
         __syncthreads();
         if (b >= B.count) return;
-        batch_solve_one<F32>(B, P, b, lds);
+        batch_solve_one<F32>(B, P, b, lds, sbuf);
     }
 }
 

@@ -181,6 +181,7 @@ int vec_grid(long long len);
 // ---- batched solve of many QPs with diagonal Q (batch.hip) ----------------------
 
 constexpr int BATCH_GRID_MAX = 2048;   // persistent workgroups (instances are queued)
+constexpr int BATCH_LDS = 6144;        // doubles of LDS per workgroup for staged operands
 
 struct BatchOut {
     int status, pad;
