@@ -87,7 +87,8 @@ typedef struct {
     int precision;            /* QP_PRECISION_FP64 (0, default) or QP_PRECISION_MIXED (1) */
     int graph_steps;          /* > 0: the inner solve's steps are launched as a captured HIP
                                  graph of this many steps (0: one launch per kernel; timing
-                                 forces 0); results are the same either way; 2 */
+                                 forces 0); results are the same either way; 0 (measured
+                                 slower: the steps are bound by the GPU, not by launches) */
     int reserved;
 } qp_params;
 

@@ -814,7 +814,7 @@ qp_params qp_params_default(void)
     p.mprgp_abar_scale = 1.9;
     p.timing = 0;
     p.precision = QP_PRECISION_FP64;
-    p.graph_steps = 2;
+    p.graph_steps = 0;
     p.reserved = 0;
     return p;
 }
