@@ -291,18 +291,21 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     // A x_ref (axref) and A' y_ref (aty, written by every check); zero until
     // the first check
     double* xref = B.xref; double* yref = B.yref; double* axref = B.axref + r0;
+    // an instance small enough keeps the operands of its products in LDS:
+    // sx (x_bar, written by the primal step) and sy (y, written by the dual
+    // step), or their differences from the reference point in mixed
+    // precision; with an inner solve also sp_ (its direction) and sxt (x_T)
+    const int stage = (qgen ? 3 * n + m : n + m) <= BATCH_LDS ? 1 : 0;
+    double* sx = sbuf;
+    double* sy = sbuf + n;
+    double* sp_ = sbuf + n + m;
+    double* sxt = sbuf + 2 * n + m;
     for (int i = tid; i < n; i += TPB) {
         const double v = clampd(0.0, lv[i], uv[i]);
         x[i] = v; xa[i] = v; xt[i] = v;
         if constexpr (F32) { xref[v0 + i] = 0.0; aty[i] = 0.0; }
+        if (stage && qgen) sxt[i] = v;
     }
-    // a closed-form instance small enough keeps the operands of its two
-    // products in LDS: sx (x_bar, written by the primal step) and sy (y,
-    // written by the dual step), or their differences from the reference
-    // point in mixed precision
-    const int stage = (!qgen && n + m <= BATCH_LDS) ? 1 : 0;
-    double* sx = sbuf;
-    double* sy = sbuf + n;
     for (int j = tid; j < m; j += TPB) {
         y[j] = 0.0; ya[j] = 0.0; yt[r0 + j] = 0.0;
         if constexpr (F32) { yref[r0 + j] = 0.0; axref[j] = 0.0; }
@@ -469,11 +472,15 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             const double abar = P.abar_scale / (normq + it);
             double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
             for (int i = tid; i < n; i += TPB) {
-                const double r = x[i] * it - c[i] -
-                                 row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
+                const double aty_i =
+                    stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
+                          : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
+                const double r = x[i] * it - c[i] - aty_i;
                 rhs[i] = r;
                 const double xi = xt[i];
-                const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - r;
+                const double qx = stage ? row_dot_lds<false>(B.qrp, B.qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
+                                        : row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i);
+                const double gi = qx + it * xi - r;
                 g[i] = gi;
                 const Split sp = split(xi, gi, lv[i], uv[i], abar);
                 st[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -491,13 +498,17 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             while (!done) {
                 for (int i = tid; i < n; i += TPB) {
                     const Split sp = split(xt[i], g[i], lv[i], uv[i], abar);
-                    p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
+                    const double pn = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
+                    p[i] = pn;
+                    if (stage) sp_[i] = pn;
                 }
                 __syncthreads();
                 double hs[3] = {0.0, 0.0, INFINITY};   // p'Hp, g'p, feasible step
                 for (int i = tid; i < n; i += TPB) {
                     const double pi = p[i], xi = xt[i];
-                    const double h = hp_dot<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i) + it * pi;
+                    const double h =
+                        (stage ? row_dot_lds<F32>(B.qrp, B.qcol, B.qval, B.qval32, sp_, v0, 0.0, v0 + i)
+                               : hp_dot<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i)) + it * pi;
                     hp[i] = h;
                     hs[0] += pi * h;
                     hs[1] += g[i] * pi;
@@ -531,6 +542,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                         us[3] += sp.phi * hp[i];
                     }
                     xt[i] = xi;
+                    if (stage) sxt[i] = xi;
                 }
                 ++inner;
                 if (kind == STEP_EXPAND) {
@@ -538,7 +550,9 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     us[0] = us[1] = us[2] = 0.0;
                     for (int i = tid; i < n; i += TPB) {
                         const double xi = xt[i];
-                        const double gi = row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) + it * xi - rhs[i];
+                        const double qx = stage ? row_dot_lds<false>(B.qrp, B.qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
+                                                : row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i);
+                        const double gi = qx + it * xi - rhs[i];
                         g[i] = gi;
                         const Split sp = split(xi, gi, lv[i], uv[i], abar);
                         us[0] += sp.phi * sp.phi + sp.beta * sp.beta;
@@ -554,7 +568,14 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 mode = !prop ? DIR_BETA : (last == STEP_CG ? DIR_CONJ : DIR_PHI);
             }
             inner_total += inner;
-            for (int i = tid; i < n; i += TPB) xbar[v0 + i] = 2.0 * xt[i] - x[i];
+            for (int i = tid; i < n; i += TPB) {
+                const double xb = 2.0 * xt[i] - x[i];
+                xbar[v0 + i] = xb;
+                if (stage) {
+                    if constexpr (F32) sx[i] = xb - xref[v0 + i];
+                    else sx[i] = xb;
+                }
+            }
             __syncthreads();
         }
         // ---- dual step and Halpern on y --------------------------------------------
