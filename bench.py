@@ -102,6 +102,27 @@ def main_batch(args, torch, P, I):
     mixed = args.precision == "mixed"
     params = P.qp_params_default(tol=args.tol, max_iter=args.max_iter,
                                  precision=P.PRECISION_MIXED if mixed else P.PRECISION_FP64)
+    # launch schedule: the autotuner's pick (timed on these instances before
+    # the warmup, outside the timed region), the library default, or given
+    sched = {}
+    if args.schedule == "auto":
+        t = time.perf_counter()
+        e = bs.tune(params)
+        sched = {"source": "autotuner", "tune_s": time.perf_counter() - t,
+                 "candidates_ms": [round(v * 1e3, 2) for v in e["seconds"]]}
+        log(f"autotuner: shape {e['shape']} ({e['threads']} threads, {e['lds']} LDS doubles, "
+            f"{e['waves_per_simd']} waves/SIMD), order {e['order']} in {sched['tune_s']:.1f}s; "
+            f"candidates {sched['candidates_ms']} ms")
+    elif args.schedule != "default":
+        sh, od = (int(v) for v in args.schedule.split(","))
+        bs.set_schedule(sh, od)
+        sched = {"source": "given"}
+    else:
+        sched = {"source": "library default"}
+    shape, order = bs.schedule()
+    threads, lds, waves = P.qp_batch_shape_info(shape)
+    sched.update({"shape": shape, "order": order, "threads": threads, "lds_doubles": lds,
+                  "waves_per_simd": waves})
     for w in range(args.warmup):
         st, sec = bs.solve(params)
         log(f"warmup {w}: {int(np.sum(st == P.OPTIMAL))}/{len(qs)} optimal in {sec * 1e3:.1f} ms")
@@ -146,6 +167,7 @@ def main_batch(args, torch, P, I):
                      "kernel": "k_batch_solve", "bytes_per_launch": nbytes, "avg_us": kernel_s * 1e6},
         "one_at_a_time": {"value": 1.0 / float(np.mean(one)), "unit": "QPs solved/s",
                           "sample": f"first {len(one)} instances, qp_solve each (FP64, same GPU)"},
+        "schedule": sched,
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -268,7 +290,7 @@ def main_serve(args, torch, P, I):
                                  precision=P.PRECISION_MIXED if mixed else P.PRECISION_FP64)
     cfg = dict(batch_lanes=args.lanes, general_lanes=args.general_lanes, single_workers=args.workers,
                batch_max_dim=args.batch_max_dim, general_max_dim=args.general_max_dim,
-               batch_linger_us=args.linger_us)
+               batch_linger_us=args.linger_us, batch_shape=args.batch_shape, batch_order=args.batch_order)
     with P.Server(params, **cfg) as srv:
         for q in (I.mpc(0), I.random_small(0, n=2000), I.portfolio(0, n_assets=10000, k_factors=50)):
             srv.wait(srv.submit(q))                              # warm-up (not timed)
@@ -367,6 +389,10 @@ def main():
                     help="arithmetic of the portfolio and batched workloads (default: mixed for them; "
                          "the large sparse workload is FP64)")
     ap.add_argument("--count", type=int, default=4096, help="instances of the batched workload")
+    ap.add_argument("--schedule", default="auto",
+                    help="batched launch schedule: auto (autotuner), default, or SHAPE,ORDER")
+    ap.add_argument("--batch-shape", type=int, default=-1, help="server batched launch shape (-1: default)")
+    ap.add_argument("--batch-order", type=int, default=-1, help="server batched queue order (-1: default)")
     ap.add_argument("--one-at-a-time", type=int, default=32,
                     help="instances of the batched workload also solved one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")

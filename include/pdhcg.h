@@ -274,6 +274,38 @@ int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds);
 
 void qp_batch_destroy(qp_batch* bt);
 
+/* ---- launch schedule of the batched solve, and its autotuner -------------
+ *
+ * One workgroup solves one instance; the schedule is the workgroup shape
+ * (threads, and doubles of LDS that hold a small instance's product
+ * operands) and the order in which workgroups take instances from the
+ * queue (0: index order, 1: largest instance first, the default).  The grid
+ * is persistent: as many workgroups as the device holds at once for the
+ * shape.  More threads per instance shorten each instance; fewer threads
+ * and less LDS let more instances run at once: which is faster depends on
+ * the instance sizes, hence the tuner.  The order never changes a result;
+ * the shape may change the last bits (a workgroup reduction groups its
+ * terms by the workgroup size), and each shape is deterministic. */
+
+/* Number of compiled shapes, and shape i's threads per workgroup, LDS
+ * doubles and the waves per SIMD its register allocation leaves room for
+ * (1: as many registers as the workgroup size allows; more: fewer registers,
+ * some spilled, more instances resident) (host outputs, may be NULL).  The
+ * default shape is 1. */
+int qp_batch_num_shapes(void);
+int qp_batch_shape_info(int32_t shape, int32_t* threads, int32_t* lds_doubles, int32_t* waves_per_simd);
+
+/* Set the schedule of later solves of bt (-1 keeps a field); get it. */
+int qp_batch_set_schedule(qp_batch* bt, int32_t shape, int32_t order);
+int qp_batch_get_schedule(const qp_batch* bt, int32_t* shape, int32_t* order);
+
+/* Autotuner: solves the batch once per candidate schedule (every shape in
+ * both orders, candidate c = 2 * shape + order) with params, keeps the
+ * fastest, solves once more with it so the batch holds its results, and
+ * returns c.  seconds (host, 2 * qp_batch_num_shapes() entries, may be NULL)
+ * receives each candidate's solve time.  Blocking; costs that many solves. */
+int qp_batch_tune(qp_batch* bt, const qp_params* params, double* seconds);
+
 /* ---- request server: continuous batching ---------------------------------
  *
  * A server takes QPs of any size as they arrive and solves them on one GPU:
@@ -304,6 +336,9 @@ typedef struct {
     int32_t general_lanes;    /* batched launches in flight for non-diagonal-Q requests; 2 */
     int32_t single_workers;   /* single-path solves in flight; 8 */
     int32_t max_batch;        /* instances per batched launch; 1024 */
+    int32_t batch_shape;      /* launch shape of the batched launches (qp_batch_set_schedule),
+                                 -1: the library default */
+    int32_t batch_order;      /* their queue order (0 or 1), -1: the library default */
     double batch_linger_us;   /* a free lane waits up to this long (from the oldest waiting
                                  request's arrival) for more requests before launching; 200 */
 } qp_server_config;

@@ -72,6 +72,7 @@ class ServerConfig(C.Structure):
     _fields_ = [("device_budget", _i64), ("batch_max_dim", _i64), ("general_max_dim", _i64),
                 ("batch_lanes", C.c_int32), ("general_lanes", C.c_int32),
                 ("single_workers", C.c_int32), ("max_batch", C.c_int32),
+                ("batch_shape", C.c_int32), ("batch_order", C.c_int32),
                 ("batch_linger_us", C.c_double)]
 
 
@@ -129,6 +130,12 @@ def lib():
         L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
+        L.qp_batch_num_shapes.argtypes = []
+        L.qp_batch_shape_info.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]
+        L.qp_batch_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.qp_batch_get_schedule.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qp_batch_tune.argtypes = [C.c_void_p, C.POINTER(QPParams), _dp]
         L.qp_server_config_default.restype = ServerConfig
         L.qp_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(QPParams), C.POINTER(C.c_void_p)]
         L.qp_server_submit.argtypes = [C.c_void_p, _i64, _i64, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp,
@@ -386,6 +393,53 @@ def qp_batch_destroy(h):
         h.value = None
 
 
+def qp_batch_num_shapes() -> int:
+    return _check(lib().qp_batch_num_shapes())
+
+
+def qp_batch_shape_info(shape):
+    """(threads per workgroup, LDS doubles, waves per SIMD) of a compiled batch shape."""
+    t, l_, w = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(lib().qp_batch_shape_info(shape, C.byref(t), C.byref(l_), C.byref(w)))
+    return t.value, l_.value, w.value
+
+
+def qp_batch_set_schedule(h, shape=-1, order=-1):
+    _check(lib().qp_batch_set_schedule(h, shape, order))
+
+
+def qp_batch_get_schedule(h):
+    s_, o = C.c_int32(0), C.c_int32(0)
+    _check(lib().qp_batch_get_schedule(h, C.byref(s_), C.byref(o)))
+    return s_.value, o.value
+
+
+def qp_batch_tune(h, params: QPParams | None = None):
+    """Time every (shape, order) on the batch; returns (best candidate, seconds per candidate)."""
+    sec = np.zeros(2 * qp_batch_num_shapes())
+    best = _check(lib().qp_batch_tune(h, None if params is None else C.byref(params), _d(sec)))
+    return best, sec
+
+
+def batch_signature(qps, params: QPParams | None = None) -> str:
+    """Key under which a tuned batch schedule is cached: instance count and
+    largest n + m (both rounded up to powers of two), whether any instance
+    has a non-diagonal Q, and the precision."""
+    def up2(v):
+        return 1 << max(0, int(v) - 1).bit_length()
+    gen = any(q.Q is not None and not _is_diagonal(q.Q) for q in qps)
+    prec = params.precision if params is not None else PRECISION_FP64
+    return (f"count={up2(len(qps))};maxdim={up2(max(q.n + q.m for q in qps))};"
+            f"general={int(gen)};precision={prec}")
+
+
+def _is_diagonal(Q) -> bool:
+    import scipy.sparse as sp
+    Q = sp.csr_matrix(Q)
+    r, c_ = Q.nonzero()
+    return bool(np.all(r == c_))
+
+
 class BatchSolver:
     """Owns a batch of instances.QP objects (diagonal or zero Q each)."""
 
@@ -405,6 +459,42 @@ class BatchSolver:
         q = self.qps[i]
         st, x, y, info = qp_batch_result(self.h, i, q.n, q.m)
         return Result(st, x, y, info)
+
+    def set_schedule(self, shape=-1, order=-1):
+        qp_batch_set_schedule(self.h, shape, order)
+
+    def schedule(self):
+        """(shape, order) of the next solve."""
+        return qp_batch_get_schedule(self.h)
+
+    def tune(self, params: QPParams | None = None, cache: str | None = None):
+        """Pick the fastest launch schedule for this batch (qp_batch_tune).
+        With `cache` (a JSON file), a schedule stored under this batch's
+        signature is reused without timing, and a new one is stored.
+        Returns {"shape", "order", "threads", "lds", "waves_per_simd",
+        "seconds", "cached"}."""
+        import json
+        key = batch_signature(self.qps, params)
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            e = table[key]
+            self.set_schedule(e["shape"], e["order"])
+            return dict(e, cached=True)
+        best, sec = qp_batch_tune(self.h, params)
+        shape, order = best // 2, best % 2
+        threads, lds, waves = qp_batch_shape_info(shape)
+        e = {"shape": shape, "order": order, "threads": threads, "lds": lds, "waves_per_simd": waves,
+             "seconds": [float(v) for v in sec]}
+        if cache:
+            table[key] = e
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(e, cached=False)
 
     def close(self):
         qp_batch_destroy(self.h)

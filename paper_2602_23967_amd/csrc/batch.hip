@@ -14,6 +14,8 @@
 // atomic is the work counter, taken once per instance.
 #include <math.h>
 
+#include <atomic>
+
 #include "device_math.h"
 #include "pdhcg_internal.h"
 
@@ -32,7 +34,7 @@ __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_read
 
 // Sum (bit j of MAXMASK clear) or max (bit set) of NR values over the
 // workgroup, in a fixed order; the result lands in every thread.
-template <int NR, unsigned MAXMASK>
+template <int NR, unsigned MAXMASK, int NT>
 __device__ void wg_reduce(double (&v)[NR], double* lds)
 {
 #pragma unroll
@@ -52,13 +54,14 @@ __device__ void wg_reduce(double (&v)[NR], double* lds)
         const int kind = ((MAXMASK >> j) & 1u) ? R_MAX : R_SUM;
         double r = lds[j];
 #pragma unroll
-        for (int w = 1; w < TPB / 64; ++w) r = rcomb(kind, r, lds[w * NR + j]);
+        for (int w = 1; w < NT / 64; ++w) r = rcomb(kind, r, lds[w * NR + j]);
         v[j] = uniform(r);
     }
     __syncthreads();
 }
 
 // sums of slots 0 and 1, minimum of slot 2, over the workgroup (in every thread)
+template <int NT>
 __device__ void wg_reduce_min3(double (&v)[3], double* lds)
 {
 #pragma unroll
@@ -78,7 +81,7 @@ __device__ void wg_reduce_min3(double (&v)[3], double* lds)
         const int kind = j == 2 ? R_MIN : R_SUM;
         double r = lds[j];
 #pragma unroll
-        for (int w = 1; w < TPB / 64; ++w) r = rcomb(kind, r, lds[w * 3 + j]);
+        for (int w = 1; w < NT / 64; ++w) r = rcomb(kind, r, lds[w * 3 + j]);
         v[j] = uniform(r);
     }
     __syncthreads();
@@ -115,6 +118,7 @@ __device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, co
     }
 }
 
+template <int NT, int LDSN>
 __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
                                 const double* mval, const int* trp, const int* tcol, const double* tval,
                                 double tol, long long max_iter, double* v, double* w, double* u, double* lds,
@@ -156,7 +160,8 @@ __device__ __forceinline__ double hp_dot(const int* rp, const int* col, const do
 }
 
 // ---- ||M_b||_2 by power iteration on M_b'M_b, one instance per workgroup ----
-__global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const int* rowoff,
+template <int NT, int LDSN>
+__global__ __launch_bounds__(NT) void k_batch_norm(int count, int* queue, const int* order, const int* rowoff,
                                                    const int* coloff, const int* mrp,
                                                    const int* mcol, const double* mval,
                                                    const int* trp, const int* tcol,
@@ -164,15 +169,16 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
                                                    long long max_iter, double* v, double* w,
                                                    double* u, double* out)
 {
-    __shared__ double lds[2 * (TPB / 64)];
-    __shared__ double sbuf[BATCH_LDS];
+    __shared__ double lds[2 * (NT / 64)];
+    __shared__ double sbuf[LDSN];
     __shared__ int s_b;
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(queue, 1);
         __syncthreads();
-        const int b = uniform_int(s_b);
+        int b = uniform_int(s_b);
         __syncthreads();
         if (b >= count) return;
+        if (order != nullptr) b = uniform_int(order[b]);
         // every value that steers control flow around a barrier is moved to
         // scalar registers: a branch the compiler sees as divergent runs both
         // sides under an exec mask, and an empty-mask side whose loop is
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
         const int skip = (sel != nullptr) ? (uniform_int(sel[b]) == 0) : 0;
         const int active = uniform_int((m > 0 && nnz > 0 && !skip) ? 1 : 0);
         double sig = 0.0;
-        if (active) sig = power_norm_wg(c0, n, r0, m, mrp, mcol, mval, trp, tcol, tval, tol, max_iter, v, w,
+        if (active) sig = power_norm_wg<NT, LDSN>(c0, n, r0, m, mrp, mcol, mval, trp, tcol, tval, tol, max_iter, v, w,
                                         u, lds, sbuf);
         if (threadIdx.x == 0) out[b] = sig;
         __syncthreads();
@@ -193,6 +199,7 @@ __global__ __launch_bounds__(TPB) void k_batch_norm(int count, int* queue, const
 
 // ||M_b||_2 of one instance by power iteration on M_b'M_b (the whole
 // workgroup; every branch below is on workgroup-uniform values)
+template <int NT, int LDSN>
 __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, const int* mcol,
                                 const double* mval, const int* trp, const int* tcol, const double* tval,
                                 double tol, long long max_iter, double* v, double* w, double* u, double* lds,
@@ -200,13 +207,13 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
 {
     // a small instance keeps v and w in LDS (the same values as the global
     // copies, gathered from LDS)
-    const int stage = (n + m <= BATCH_LDS) ? 1 : 0;
+    const int stage = (n + m <= LDSN) ? 1 : 0;
     double* sv = sbuf;
     double* sw = sbuf + n;
     {
         // start vector: SplitMix64 of the local index (seed 0), in [-1, 1)
         double acc[1] = {0.0};
-        for (int j = threadIdx.x; j < n; j += TPB) {
+        for (int j = threadIdx.x; j < n; j += NT) {
             unsigned long long z = (static_cast<unsigned long long>(j) + 1ull) * 0x9E3779B97F4A7C15ull;
             z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
             z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -215,9 +222,9 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
             v[c0 + j] = val;
             acc[0] += val * val;
         }
-        wg_reduce<1, 0u>(acc, lds);
+        wg_reduce<1, 0u, NT>(acc, lds);
         const double nv = sqrt(acc[0]);
-        for (int j = threadIdx.x; j < n; j += TPB) {
+        for (int j = threadIdx.x; j < n; j += NT) {
             const double vj = v[c0 + j] / nv;
             v[c0 + j] = vj;
             if (stage) sv[j] = vj;
@@ -226,27 +233,27 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
         double sig = 0.0, prev = 0.0;
         for (long long it = 1; it <= max_iter; ++it) {
             acc[0] = 0.0;
-            for (int i = threadIdx.x; i < m; i += TPB) {
+            for (int i = threadIdx.x; i < m; i += NT) {
                 const double s = stage ? row_dot_lds<false>(mrp, mcol, mval, nullptr, sv, c0, 0.0, r0 + i)
                                        : row_dot(mrp, mcol, mval, v, r0 + i);
                 w[r0 + i] = s;
                 if (stage) sw[i] = s;
                 acc[0] += s * s;
             }
-            wg_reduce<1, 0u>(acc, lds);
+            wg_reduce<1, 0u, NT>(acc, lds);
             sig = sqrt(acc[0]);
             if (sig == 0.0) break;
             acc[0] = 0.0;
-            for (int i = threadIdx.x; i < n; i += TPB) {
+            for (int i = threadIdx.x; i < n; i += NT) {
                 const double s = stage ? row_dot_lds<false>(trp, tcol, tval, nullptr, sw, r0, 0.0, c0 + i)
                                        : row_dot(trp, tcol, tval, w, c0 + i);
                 u[c0 + i] = s;
                 acc[0] += s * s;
             }
-            wg_reduce<1, 0u>(acc, lds);
+            wg_reduce<1, 0u, NT>(acc, lds);
             const double nu = sqrt(acc[0]);
             if (nu == 0.0) break;
-            for (int i = threadIdx.x; i < n; i += TPB) {
+            for (int i = threadIdx.x; i < n; i += NT) {
                 const double vi = u[c0 + i] / nu;
                 v[c0 + i] = vi;
                 if (stage) sv[i] = vi;
@@ -261,8 +268,8 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
 
 // ---- the solve -----------------------------------------------------------------
 
-template <bool F32>
-__device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds, double* sbuf)
+template <int NT, int LDSN, bool F32>
+__device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds, double* sbuf)
 {
     // per-instance values in scalar registers: the branches on them (closed
     // form vs inner solve, certificates) must be seen as uniform, or the
@@ -295,18 +302,18 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     // sx (x_bar, written by the primal step) and sy (y, written by the dual
     // step), or their differences from the reference point in mixed
     // precision; with an inner solve also sp_ (its direction) and sxt (x_T)
-    const int stage = (qgen ? 3 * n + m : n + m) <= BATCH_LDS ? 1 : 0;
+    const int stage = (qgen ? 3 * n + m : n + m) <= LDSN ? 1 : 0;
     double* sx = sbuf;
     double* sy = sbuf + n;
     double* sp_ = sbuf + n + m;
     double* sxt = sbuf + 2 * n + m;
-    for (int i = tid; i < n; i += TPB) {
+    for (int i = tid; i < n; i += NT) {
         const double v = clampd(0.0, lv[i], uv[i]);
         x[i] = v; xa[i] = v; xt[i] = v;
         if constexpr (F32) { xref[v0 + i] = 0.0; aty[i] = 0.0; }
         if (stage && qgen) sxt[i] = v;
     }
-    for (int j = tid; j < m; j += TPB) {
+    for (int j = tid; j < m; j += NT) {
         y[j] = 0.0; ya[j] = 0.0; yt[r0 + j] = 0.0;
         if constexpr (F32) { yref[r0 + j] = 0.0; axref[j] = 0.0; }
         if (stage) sy[j] = 0.0;
@@ -328,7 +335,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             // max slots: 0 1 4 7 8 9 13 15, the rest sums
             constexpr unsigned kinds = (1u << 0) | (1u << 1) | (1u << 4) | (1u << 7) | (1u << 8) |
                                        (1u << 9) | (1u << 13) | (1u << 15);
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += NT) {
                 const double s = row_dot(B.trp, B.tcol, B.tval, yt, v0 + i);
                 aty[i] = s;
                 a[0] = rcomb(R_MAX, a[0], fabs(s));
@@ -340,7 +347,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     a[3] += supp_abs(-wh, lv[i], uv[i]);
                 }
             }
-            for (int j = tid; j < m; j += TPB) {
+            for (int j = tid; j < m; j += NT) {
                 const double s = row_dot(B.arp, B.acol, B.aval, B.xt, r0 + j);
                 if constexpr (F32) axref[j] = s;
                 a[4] = rcomb(R_MAX, a[4], fabs(s - clampd(s, lc[j], uc[j])));
@@ -354,7 +361,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 }
             }
             __syncthreads();
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += NT) {
                 const double xi = xt[i], l = lv[i], u = uv[i];
                 const double qx = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) : qd[i] * xi;
                 const double r = qx + c[i] + aty[i];
@@ -375,10 +382,10 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             if constexpr (F32) {
                 // the new reference point: (x_T, y_T), whose products with A
                 // and A' this check computed in FP64
-                for (int i = tid; i < n; i += TPB) xref[v0 + i] = xt[i];
-                for (int j = tid; j < m; j += TPB) yref[r0 + j] = yt[r0 + j];
+                for (int i = tid; i < n; i += NT) xref[v0 + i] = xt[i];
+                for (int j = tid; j < m; j += NT) yref[r0 + j] = yt[r0 + j];
             }
-            wg_reduce<16, kinds>(a, lds);
+            wg_reduce<16, kinds, NT>(a, lds);
             rp_ = a[4] / bscale;
             double sd = a[9] > a[0] ? a[9] : a[0];
             sd = sd > cmax ? sd : cmax;
@@ -435,12 +442,12 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             }
             if (status) break;
             if (restart) {
-                for (int i = tid; i < n; i += TPB) { x[i] = xt[i]; xa[i] = xt[i]; }
-                for (int j = tid; j < m; j += TPB) { y[j] = yt[r0 + j]; ya[j] = yt[r0 + j]; }
+                for (int i = tid; i < n; i += NT) { x[i] = xt[i]; xa[i] = xt[i]; }
+                for (int j = tid; j < m; j += NT) { y[j] = yt[r0 + j]; ya[j] = yt[r0 + j]; }
             }
             if (stage) {
                 // y after a restart, and (mixed) its difference from the new reference
-                for (int j = tid; j < m; j += TPB) {
+                for (int j = tid; j < m; j += NT) {
                     if constexpr (F32) sy[j] = y[j] - yref[r0 + j];
                     else sy[j] = y[j];
                 }
@@ -452,7 +459,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
 
         if (!qgen) {
             // ---- primal step: closed form (Section 2.2) and x_bar -----------------
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += NT) {
                 const double s =
                     stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
                           : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
@@ -471,7 +478,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             // ---- primal step: boxed CG (MPRGP) on 1/2 x'(Q + I/tau)x - rhs'x -----
             const double abar = P.abar_scale / (normq + it);
             double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += NT) {
                 const double aty_i =
                     stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
                           : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
@@ -487,7 +494,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 st[1] += sp.beta * sp.beta;
                 st[2] += sp.phit * sp.phi;
             }
-            wg_reduce<3, 0u>(st, lds);
+            wg_reduce<3, 0u, NT>(st, lds);
             if (isinf(eps) && P.eps_fixed <= 0.0) eps = fmax(P.gamma_inner * sqrt(st[0]), P.eps_min);
             const double eps_use = P.eps_fixed > 0.0 ? P.eps_fixed : eps;
             long long inner = 0;
@@ -496,7 +503,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             bool done = sqrt(st[0]) <= eps_use || P.max_inner <= 0;
             int mode = (st[1] <= P.mprgp_gamma * P.mprgp_gamma * st[2]) ? DIR_PHI : DIR_BETA;
             while (!done) {
-                for (int i = tid; i < n; i += TPB) {
+                for (int i = tid; i < n; i += NT) {
                     const Split sp = split(xt[i], g[i], lv[i], uv[i], abar);
                     const double pn = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
                     p[i] = pn;
@@ -504,7 +511,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 }
                 __syncthreads();
                 double hs[3] = {0.0, 0.0, INFINITY};   // p'Hp, g'p, feasible step
-                for (int i = tid; i < n; i += TPB) {
+                for (int i = tid; i < n; i += NT) {
                     const double pi = p[i], xi = xt[i];
                     const double h =
                         (stage ? row_dot_lds<F32>(B.qrp, B.qcol, B.qval, B.qval32, sp_, v0, 0.0, v0 + i)
@@ -517,7 +524,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                     else if (pi < 0.0 && isfinite(uv[i])) fs = (xi - uv[i]) / pi;
                     hs[2] = fmin(hs[2], fs);
                 }
-                wg_reduce_min3(hs, lds);
+                wg_reduce_min3<NT>(hs, lds);
                 if (!(hs[0] > 0.0)) break;
                 const double af = hs[2] < 0.0 ? 0.0 : hs[2];
                 const double acg = hs[1] / hs[0];
@@ -527,7 +534,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 else if (acg <= af) { kind = STEP_CG; alpha = acg; }
                 else { kind = STEP_EXPAND; alpha = af; }
                 double us[4] = {0.0, 0.0, 0.0, 0.0};   // stats and phi'Hp
-                for (int i = tid; i < n; i += TPB) {
+                for (int i = tid; i < n; i += NT) {
                     const double l = lv[i], u = uv[i];
                     double xi = clampd(xt[i] - alpha * p[i], l, u);
                     const double gi = g[i] - alpha * hp[i];
@@ -548,7 +555,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 if (kind == STEP_EXPAND) {
                     __syncthreads();
                     us[0] = us[1] = us[2] = 0.0;
-                    for (int i = tid; i < n; i += TPB) {
+                    for (int i = tid; i < n; i += NT) {
                         const double xi = xt[i];
                         const double qx = stage ? row_dot_lds<false>(B.qrp, B.qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
                                                 : row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i);
@@ -560,7 +567,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                         us[2] += sp.phit * sp.phi;
                     }
                 }
-                wg_reduce<4, 0u>(us, lds);
+                wg_reduce<4, 0u, NT>(us, lds);
                 if (kind == STEP_CG) gam = us[3] / hs[0];
                 last = kind;
                 done = sqrt(us[0]) <= eps_use || inner >= P.max_inner;
@@ -568,7 +575,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 mode = !prop ? DIR_BETA : (last == STEP_CG ? DIR_CONJ : DIR_PHI);
             }
             inner_total += inner;
-            for (int i = tid; i < n; i += TPB) {
+            for (int i = tid; i < n; i += NT) {
                 const double xb = 2.0 * xt[i] - x[i];
                 xbar[v0 + i] = xb;
                 if (stage) {
@@ -583,7 +590,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
         const double th = P.theta;
         double a[7] = {0, 0, 0, 0, 0, 0, 0};
         constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
-        for (int j = tid; j < m; j += TPB) {
+        for (int j = tid; j < m; j += NT) {
             const double s =
                 stage ? row_dot_lds<F32>(B.arp, B.acol, B.aval, B.aval32, sx, v0, axref[j], r0 + j)
                       : row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j);
@@ -608,7 +615,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
             }
         }
         // ---- Halpern on x ---------------------------------------------------------
-        for (int i = tid; i < n; i += TPB) {
+        for (int i = tid; i < n; i += NT) {
             const double xti = xt[i], xi = x[i];
             const double dx = xti - xi;
             a[0] += dx * dx;
@@ -620,7 +627,7 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
                 a[6] += c[i] * di;
             }
         }
-        wg_reduce<7, kinds7>(a, lds);
+        wg_reduce<7, kinds7, NT>(a, lds);
         ndx2 = a[0];
         ndy2 = a[1];
         if (P.eps_fixed <= 0.0) eps = fmin(eps, fmax(P.gamma_inner * omega * sqrt(ndx2) / tau, P.eps_min));
@@ -648,44 +655,125 @@ __device__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, 
     __syncthreads();
 }
 
-template <bool F32>
-__global__ __launch_bounds__(TPB) void k_batch_solve(BatchDev B, BatchParams P)
+// WPE: waves per SIMD the register allocation must allow (1: no limit
+// beyond the workgroup size; more trades spills for resident instances)
+template <int NT, int LDSN, int WPE, bool F32>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_batch_solve(BatchDev B, BatchParams P)
 {
-    __shared__ double lds[16 * (TPB / 64)];
-    __shared__ double sbuf[BATCH_LDS];
+    __shared__ double lds[16 * (NT / 64)];
+    __shared__ double sbuf[LDSN];
     __shared__ int s_b;
     for (;;) {
         if (threadIdx.x == 0) s_b = atomicAdd(B.queue, 1);
         __syncthreads();
-        const int b = uniform_int(s_b);
+        int b = uniform_int(s_b);
         __syncthreads();
         if (b >= B.count) return;
-        batch_solve_one<F32>(B, P, b, lds, sbuf);
+        if (B.order != nullptr) b = uniform_int(B.order[b]);
+        batch_solve_one<NT, LDSN, F32>(B, P, b, lds, sbuf);
     }
 }
 
-int batch_grid(int count)
+// ---- launch shapes ---------------------------------------------------------------
+// (threads per workgroup, LDS doubles for staged operands): more threads per
+// instance against more instances resident per CU; which wins depends on the
+// instance sizes, so the host can time them on a batch (the autotuner) or use
+// the default.
+
+template <int NT, int LDSN, int WPE, bool F32>
+hipError_t solve_shape(const BatchDev& B, const BatchParams& P, int grid, hipStream_t s)
 {
-    const int g = count < BATCH_GRID_MAX ? count : BATCH_GRID_MAX;
-    return g < 1 ? 1 : g;
+    k_batch_solve<NT, LDSN, WPE, F32><<<grid, NT, 0, s>>>(B, P);
+    return hipGetLastError();
 }
 
-hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* coloff,
+template <int NT, int LDSN, int WPE>
+hipError_t norm_shape(const BatchDev& B, const int* rowoff, const int* coloff, const int* mrp,
+                      const int* mcol, const double* mval, const int* trp, const int* tcol,
+                      const double* tval, const int* sel, double tol, long long max_iter, double* v,
+                      double* w, double* u, double* out, int grid, hipStream_t s)
+{
+    k_batch_norm<NT, LDSN><<<grid, NT, 0, s>>>(B.count, B.queue, B.order, rowoff, coloff, mrp, mcol, mval,
+                                               trp, tcol, tval, sel, tol, max_iter, v, w, u, out);
+    return hipGetLastError();
+}
+
+template <int NT, int LDSN, int WPE>
+int resident_per_cu(int which)
+{
+    int nb = 0;
+    hipError_t e;
+    if (which == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, false>, NT, 0);
+    else if (which == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, true>, NT, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_norm<NT, LDSN>, NT, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+#define PDHCG_BATCH_SHAPES(X) \
+    X(512, 8192, 1) X(256, 6144, 1) X(256, 2048, 1) X(256, 2048, 4) X(128, 1536, 1) X(128, 1536, 4) X(64, 1536, 1) X(64, 1024, 4)
+
+const BatchShape* batch_shapes(int* count)
+{
+#define PDHCG_SHAPE_ENTRY(T_, L_, W_) {T_, L_, W_},
+    static const BatchShape tab[] = {PDHCG_BATCH_SHAPES(PDHCG_SHAPE_ENTRY)};
+#undef PDHCG_SHAPE_ENTRY
+    *count = (int)(sizeof(tab) / sizeof(tab[0]));
+    return tab;
+}
+
+// persistent grid of a shape: the workgroups one pass of the device holds
+// (occupancy x CUs), at most one per instance; which: 0 FP64 solve, 1 mixed
+// solve, 2 norm kernel
+int batch_grid(int shape, int which, int count)
+{
+    static const int cus = [] {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+            return c;
+        return 256;
+    }();
+    static std::atomic<int> occ[16][3];   // resident workgroups per CU, 0 = not asked yet
+    if (shape < 0 || shape >= 16 || which < 0 || which > 2) return 1;
+    int per = occ[shape][which].load(std::memory_order_relaxed);
+    if (per == 0) {
+        int k = 0;
+#define PDHCG_SHAPE_OCC(T_, L_, W_) if (k++ == shape) per = resident_per_cu<T_, L_, W_>(which);
+        PDHCG_BATCH_SHAPES(PDHCG_SHAPE_OCC)
+#undef PDHCG_SHAPE_OCC
+        if (per < 1) per = 1;
+        occ[shape][which].store(per, std::memory_order_relaxed);
+    }
+    const long long g = (long long)per * cus;
+    const long long r = count < g ? count : g;
+    return r < 1 ? 1 : (int)r;
+}
+
+hipError_t launch_batch_norm(const BatchDev& B, int shape, const int* rowoff, const int* coloff,
                              const int* mrp, const int* mcol, const double* mval,
                              const int* trp, const int* tcol, const double* tval, const int* sel,
                              double tol, long long max_iter, double* v, double* w, double* u,
                              double* out, hipStream_t s)
 {
-    k_batch_norm<<<batch_grid(B.count), TPB, 0, s>>>(B.count, B.queue, rowoff, coloff, mrp, mcol, mval,
-                                                     trp, tcol, tval, sel, tol, max_iter, v, w, u, out);
-    return hipGetLastError();
+    const int grid = batch_grid(shape, 2, B.count);
+    int k = 0;
+#define PDHCG_SHAPE_NORM(T_, L_, W_) \
+    if (k++ == shape) return norm_shape<T_, L_, W_>(B, rowoff, coloff, mrp, mcol, mval, trp, tcol, tval, sel, tol, max_iter, v, w, u, out, grid, s);
+    PDHCG_BATCH_SHAPES(PDHCG_SHAPE_NORM)
+#undef PDHCG_SHAPE_NORM
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s)
+hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, int shape, hipStream_t s)
 {
-    if (B.aval32) k_batch_solve<true><<<batch_grid(B.count), TPB, 0, s>>>(B, P);
-    else k_batch_solve<false><<<batch_grid(B.count), TPB, 0, s>>>(B, P);
-    return hipGetLastError();
+    const bool f32 = B.aval32 != nullptr;
+    const int grid = batch_grid(shape, f32 ? 1 : 0, B.count);
+    int k = 0;
+#define PDHCG_SHAPE_SOLVE(T_, L_, W_) \
+    if (k++ == shape) return f32 ? solve_shape<T_, L_, W_, true>(B, P, grid, s) : solve_shape<T_, L_, W_, false>(B, P, grid, s);
+    PDHCG_BATCH_SHAPES(PDHCG_SHAPE_SOLVE)
+#undef PDHCG_SHAPE_SOLVE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace pdhcg

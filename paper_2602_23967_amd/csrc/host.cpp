@@ -1177,6 +1177,10 @@ struct qp_batch {
     std::vector<void*> allocs;
     std::vector<BatchOut> out;
     std::vector<double> norm_A;
+    // launch schedule: shape (index into the compiled table) and queue order
+    // (0 index order, 1 largest instance first; dorder holds that permutation)
+    int shape = pdhcg::BATCH_SHAPE_DEFAULT, order = 1;
+    const int* dorder = nullptr;
     int solved = 0;
     double setup_seconds = 0.0, solve_seconds = 0.0;
 };
@@ -1366,6 +1370,20 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
     for (double** p : mv)
         if ((rc = balloc(bt, p, (size_t)m))) return bail(rc);
     if ((rc = balloc(bt, &B.queue, 1)) || (rc = balloc(bt, &B.out, (size_t)count))) return bail(rc);
+    {
+        // largest instance first (nonzeros of A and Q plus n + m), ties in
+        // index order: a longest-processing-time-first queue, so the launch
+        // does not end on one large instance started last
+        std::vector<int64_t> work(count);
+        for (int64_t i = 0; i < count; ++i)
+            work[i] = (Ap[row_off[i + 1]] - Ap[row_off[i]]) + (Qp[var_off[i + 1]] - Qp[var_off[i]]) +
+                      (var_off[i + 1] - var_off[i]) + (row_off[i + 1] - row_off[i]);
+        std::vector<int> perm(count);
+        for (int64_t i = 0; i < count; ++i) perm[i] = (int)i;
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b_) { return work[a] > work[b_]; });
+        if ((rc = bupload(bt, &bt->dorder, perm.data(), perm.size()))) return bail(rc);
+        B.order = bt->dorder;
+    }
 
     // per-instance scalars: ||A_i||_2 on the device, the rest here
     double* dnorm = nullptr;
@@ -1373,7 +1391,7 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
     const qp_params dp = qp_params_default();
     if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemsetAsync failed"));
-    if (launch_batch_norm(B, B.roff, B.voff, B.arp, B.acol, B.aval, B.trp, B.tcol, B.tval, nullptr,
+    if (launch_batch_norm(B, BATCH_SHAPE_DEFAULT, B.roff, B.voff, B.arp, B.acol, B.aval, B.trp, B.tcol, B.tval, nullptr,
                           dp.power_tol, dp.power_max_iter, B.x, B.y, B.xt, dnorm, bt->stream) != hipSuccess ||
         hipStreamSynchronize(bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
@@ -1387,7 +1405,7 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
         if ((rc = bupload(bt, &dsel, qgen.data(), (size_t)count))) return bail(rc);
         B.qgen = dsel;
         if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess ||
-            launch_batch_norm(B, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
+            launch_batch_norm(B, BATCH_SHAPE_DEFAULT, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
                               dp.power_tol, dp.power_max_iter, B.x, B.xa, B.xt, dnorm, bt->stream) != hipSuccess ||
             hipStreamSynchronize(bt->stream) != hipSuccess ||
             copy_wait(normq_raw.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost, bt->stream) != hipSuccess)
@@ -1464,7 +1482,8 @@ int batch_launch(qp_batch* bt, const qp_params* params)
     P.mprgp_gamma = p.mprgp_gamma; P.abar_scale = p.mprgp_abar_scale; P.max_inner = p.max_inner;
     bt->t_launch = now_s();
     HIPCHK(hipMemsetAsync(bt->B.queue, 0, sizeof(int), bt->stream));
-    HIPCHK(launch_batch_solve(bt->B, P, bt->stream));
+    bt->B.order = bt->order ? bt->dorder : nullptr;
+    HIPCHK(launch_batch_solve(bt->B, P, bt->shape, bt->stream));
     HIPCHK(hipEventRecord(bt->done, bt->stream));
     return 0;
 }
@@ -1555,6 +1574,66 @@ int qp_batch_solve(qp_batch* bt, const qp_params* params)
     rc = batch_finish(bt);
     if (rc >= 0) g_err.clear();
     return rc;
+}
+
+int qp_batch_num_shapes(void)
+{
+    int count = 0;
+    pdhcg::batch_shapes(&count);
+    return count;
+}
+
+int qp_batch_shape_info(int32_t shape, int32_t* threads, int32_t* lds_doubles, int32_t* waves_per_simd)
+{
+    int count = 0;
+    const pdhcg::BatchShape* tab = pdhcg::batch_shapes(&count);
+    if (shape < 0 || shape >= count) return fail(QP_ERR_INVALID_ARG, "no such batch shape");
+    if (threads) *threads = tab[shape].threads;
+    if (lds_doubles) *lds_doubles = tab[shape].lds;
+    if (waves_per_simd) *waves_per_simd = tab[shape].waves_per_simd;
+    return 0;
+}
+
+int qp_batch_set_schedule(qp_batch* bt, int32_t shape, int32_t order)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    if (shape < -1 || shape >= qp_batch_num_shapes()) return fail(QP_ERR_INVALID_ARG, "no such batch shape");
+    if (order < -1 || order > 1) return fail(QP_ERR_INVALID_ARG, "order must be 0, 1 or -1");
+    if (shape >= 0) bt->shape = shape;
+    if (order >= 0) bt->order = order;
+    g_err.clear();
+    return 0;
+}
+
+int qp_batch_get_schedule(const qp_batch* bt, int32_t* shape, int32_t* order)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    if (shape) *shape = bt->shape;
+    if (order) *order = bt->order;
+    return 0;
+}
+
+int qp_batch_tune(qp_batch* bt, const qp_params* params, double* seconds)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    const int ns = qp_batch_num_shapes();
+    int best = -1;
+    double tbest = INFINITY;
+    for (int c = 0; c < 2 * ns; ++c) {
+        bt->shape = c / 2;
+        bt->order = c % 2;
+        const int rc = qp_batch_solve(bt, params);
+        if (rc < 0) return rc;
+        if (seconds) seconds[c] = bt->solve_seconds;
+        if (bt->solve_seconds < tbest) { tbest = bt->solve_seconds; best = c; }
+    }
+    bt->shape = best / 2;
+    bt->order = best % 2;
+    // leave the batch holding the chosen schedule's results
+    const int rc = qp_batch_solve(bt, params);
+    if (rc < 0) return rc;
+    g_err.clear();
+    return best;
 }
 
 int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info* info)

@@ -180,8 +180,14 @@ int vec_grid(long long len);
 
 // ---- batched solve of many QPs with diagonal Q (batch.hip) ----------------------
 
-constexpr int BATCH_GRID_MAX = 2048;   // persistent workgroups (instances are queued)
-constexpr int BATCH_LDS = 6144;        // doubles of LDS per workgroup for staged operands
+// launch shape of the batched kernels: threads per workgroup (one instance
+// per workgroup) and doubles of LDS for an instance's staged operands
+struct BatchShape {
+    int threads, lds, waves_per_simd;
+};
+// the table of compiled shapes (*count entries)
+const BatchShape* batch_shapes(int* count);
+constexpr int BATCH_SHAPE_DEFAULT = 1;   // 256 threads, 6144 doubles
 
 struct BatchOut {
     int status, pad;
@@ -199,6 +205,7 @@ struct BatchParams {
 struct BatchDev {
     int count = 0;
     int* queue = nullptr;                       // work counter (instances taken)
+    const int* order = nullptr;                 // queue position -> instance (NULL: index order)
     const int *voff = nullptr, *roff = nullptr; // count + 1 each
     const int *arp = nullptr, *acol = nullptr;  // A, global indices
     const double* aval = nullptr;
@@ -224,16 +231,18 @@ struct BatchDev {
     BatchOut* out = nullptr;
 };
 
-int batch_grid(int count);
+// persistent grid of a shape (which: 0 FP64 solve, 1 mixed solve, 2 norm):
+// the workgroups the device holds at once, at most `count`
+int batch_grid(int shape, int which, int count);
 // ||M_b||_2 per instance by power iteration on M_b'M_b: M (rows given by
 // rowoff, columns by coloff) and its transpose Mt; instances with sel[b] == 0
 // get 0 (sel may be NULL)
-hipError_t launch_batch_norm(const BatchDev& B, const int* rowoff, const int* coloff,
+hipError_t launch_batch_norm(const BatchDev& B, int shape, const int* rowoff, const int* coloff,
                              const int* mrp, const int* mcol, const double* mval,
                              const int* trp, const int* tcol, const double* tval, const int* sel,
                              double tol, long long max_iter, double* v, double* w, double* u,
                              double* out, hipStream_t s);
-hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, hipStream_t s);
+hipError_t launch_batch_solve(const BatchDev& B, const BatchParams& P, int shape, hipStream_t s);
 // dst[i] = (float)src[i]
 hipError_t launch_to_f32(const double* src, float* dst, long long len, hipStream_t s);
 

@@ -242,3 +242,28 @@ def test_batch_rejects_long_rows():
     _bad(lambda: P.qp_batch_create(2, vo, ro, big.Q, big.A, big.c, big.b, big.sense, big.lb, big.ub),
          P.ERR_INVALID_ARG)
     assert "QP_BATCH_MAX_ROW" in P.qp_last_error()
+
+
+def test_batch_shape_table_and_schedule_validation():
+    import ctypes as C
+    ns = P.qp_batch_num_shapes()
+    assert ns >= 2
+    shapes = [P.qp_batch_shape_info(i) for i in range(ns)]
+    assert shapes[1] == (256, 6144, 1)   # the default shape
+    for t, l_, w in shapes:
+        # whole wavefronts; staged operands leave room in the 160 KiB of LDS;
+        # 1..8 waves per SIMD
+        assert t % 64 == 0 and 64 <= t <= 1024 and 0 < l_ * 8 <= 128 * 1024 and 1 <= w <= 8
+    assert len(set(shapes)) == ns
+    for bad in (-1, ns):
+        with pytest.raises(P.QPError):
+            P.qp_batch_shape_info(bad)
+    L = P.lib()
+    assert L.qp_batch_set_schedule(None, 0, 0) == P.ERR_INVALID_ARG
+    assert L.qp_batch_tune(None, None, None) == P.ERR_INVALID_ARG
+    h = C.c_void_p()
+    for kw in ({"batch_shape": ns}, {"batch_shape": -2}, {"batch_order": 2}):
+        bad = P.qp_server_config_default(**kw)
+        assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
+    c = P.qp_server_config_default()
+    assert c.batch_shape == -1 and c.batch_order == -1

@@ -137,3 +137,62 @@ def test_batch_general_q_matches_single_path(torch):
     assert gb.status == gs.status == P.OPTIMAL
     assert gb.info["inner_iterations"] > 0
     assert gb.info["primal_obj"] == pytest.approx(gs.info["primal_obj"], rel=1e-6)
+
+
+@pytest.fixture(scope="module")
+def sched_mix():
+    qs = [I.mpc(i) for i in range(40, 46)]
+    qs += [I.random_small(3, n=300), I.mpc(102, infeasible=True), I.tiny_lp(5)]
+    ref = [oracle.solve(q, max_iter=100000) for q in qs]
+    return qs, ref
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_batch_every_schedule_matches_oracle(torch, sched_mix, precision):
+    """Every compiled launch shape in both queue orders: the order changes
+    no bit; each shape gives the oracle's status, a 1e-6 KKT point and the
+    oracle's objective."""
+    qs, ref = sched_mix
+    params = P.qp_params_default(precision=precision)
+    with P.BatchSolver(qs) as bs:
+        for shape in range(P.qp_batch_num_shapes()):
+            res = {}
+            for order in (0, 1):
+                bs.set_schedule(shape, order)
+                assert bs.schedule() == (shape, order)
+                bs.solve(params)
+                res[order] = [bs.result(i) for i in range(len(qs))]
+            print(f"shape {shape} {P.qp_batch_shape_info(shape)}: "
+                  f"iterations {[r.info['iterations'] for r in res[0]]}", flush=True)
+            for a, b in zip(res[0], res[1]):
+                assert a.status == b.status and a.info["iterations"] == b.info["iterations"]
+                assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+            for q, g, o in zip(qs, res[0], ref):
+                assert g.status == o.status, (shape, q.name, g.status_name, o.status_name)
+                if o.status == oracle.OPTIMAL:
+                    k = oracle.kkt(q, g.x, g.y)
+                    assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6, (shape, q.name, k)
+                    assert g.info["primal_obj"] == pytest.approx(o.info["primal_obj"], rel=1e-6, abs=1e-6)
+
+
+def test_batch_tune_picks_fastest_and_caches(torch, tmp_path):
+    qs = [I.mpc(i) for i in range(500, 564)]
+    cache = str(tmp_path / "schedules.json")
+    ns = P.qp_batch_num_shapes()
+    with P.BatchSolver(qs) as bs:
+        e = bs.tune(cache=cache)
+        print(f"tuned: shape {e['shape']} ({e['threads']} threads, {e['lds']} LDS doubles), "
+              f"order {e['order']}; seconds {[round(s * 1e3, 1) for s in e['seconds']]} ms", flush=True)
+        assert not e["cached"] and len(e["seconds"]) == 2 * ns
+        assert all(s > 0 for s in e["seconds"])
+        assert e["seconds"][2 * e["shape"] + e["order"]] == min(e["seconds"])
+        assert bs.schedule() == (e["shape"], e["order"])
+        st, _ = P.qp_batch_statuses(bs.h, len(qs))
+        assert np.all(st == P.OPTIMAL)
+        g = bs.result(3)
+        k = oracle.kkt(qs[3], g.x, g.y)
+        assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6
+    with P.BatchSolver(qs) as bs2:
+        e2 = bs2.tune(cache=cache)
+        assert e2["cached"] and (e2["shape"], e2["order"]) == (e["shape"], e["order"])
+        assert bs2.schedule() == (e["shape"], e["order"])

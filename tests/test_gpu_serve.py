@@ -129,3 +129,25 @@ def test_serve_errors(torch):
         with pytest.raises(P.QPError) as e:
             P.qp_server_submit(srv.h, q.n, q.m, q.Q, q.A, q.c, q.b, b"X" * q.m, q.lb, q.ub)
         assert e.value.code == P.ERR_INVALID_ARG
+
+
+def test_serve_with_a_chosen_batch_schedule(torch):
+    """A server configured with a non-default launch shape and index-order
+    queue gives each batched request the result that shape gives it alone."""
+    qs = [I.mpc(600 + i) for i in range(12)]
+    params = P.qp_params_default(precision=P.PRECISION_MIXED)
+    shape = P.qp_batch_num_shapes() - 1
+    with P.Server(params, batch_lanes=2, single_workers=1, batch_shape=shape, batch_order=0) as srv:
+        ids = [srv.submit(q) for q in qs]
+        out = []
+        for rid in ids:
+            assert srv.wait(rid, 120.0) > 0
+            out.append(srv.result(rid))
+    for q, (g, t) in zip(qs, out):
+        assert t["route"] == 0
+        with P.BatchSolver([q]) as bs:
+            bs.set_schedule(shape, 0)
+            bs.solve(params)
+            a = bs.result(0)
+        assert g.status == a.status == P.OPTIMAL, q.name
+        assert np.array_equal(g.x, a.x) and np.array_equal(g.y, a.y), q.name
