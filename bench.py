@@ -44,12 +44,22 @@ def kernels_digest():
     return h.hexdigest()[:16]
 
 
-def hp_bytes(n, nnz_q):
+def bound_bytes(q):
+    """Bytes per variable the kernels read for the box (l_v, u_v): 0 when
+    every variable has the same pair, 1 (a class byte) for at most 256
+    distinct pairs, 16 otherwise -- the library's storage rule."""
+    lb = np.full(q.n, -np.inf) if q.lb is None else np.asarray(q.lb, dtype=np.float64)
+    ub = np.full(q.n, np.inf) if q.ub is None else np.asarray(q.ub, dtype=np.float64)
+    pairs = np.unique(np.stack([lb.view(np.uint64), ub.view(np.uint64)], axis=1), axis=0)
+    return 0 if len(pairs) == 1 else (1 if len(pairs) <= 256 else 16)
+
+
+def hp_bytes(n, nnz_q, bb=16):
     """Algorithmic HBM bytes of one launch of the inner H p kernel:
     CSR values and columns (12 B per nonzero), int32 row pointers, the
-    gathered operand p once, the epilogue reads g, x, l_v, u_v and the
-    write of Hp (8 B each per row)."""
-    return 12 * nnz_q + 4 * (n + 1) + 8 * n * 6
+    gathered operand p once, the epilogue's reads of g and x and the write
+    of Hp (8 B each per row), and the box (bb bytes per row, bound_bytes)."""
+    return 12 * nnz_q + 4 * (n + 1) + 8 * n * 4 + bb * n
 
 
 def cpu_baseline(q, gpu_units_per_solve, sample_iters):
@@ -188,12 +198,13 @@ def portfolio_bytes(q, fam, vb):
     (vb = bytes per nonzero: 12 in FP64, 8 with FP32 values and int32
     columns).  rhs: A'y fused with the closed-form primal step, x_bar and the
     Halpern average of x -- the nonzeros, row pointers, y gathered once, x,
-    c, q, l_v, u_v and the x anchor read, x_T, x_bar and x written.  dual:
+    c, q, the x anchor and the box (bound_bytes) read, x_T, x_bar and x
+    written.  dual:
     A x_bar fused with the dual step and Halpern on y -- the nonzeros, row
     pointers, x_bar gathered once, y, y anchor, l_c, u_c read, y_T and y
     written."""
     if fam == "rhs":
-        return vb * q.nnz_A + 4 * (q.n + 1) + 8 * q.m + 8 * q.n * 9
+        return vb * q.nnz_A + 4 * (q.n + 1) + 8 * q.m + 8 * q.n * 7 + bound_bytes(q) * q.n
     return vb * q.nnz_A + 4 * (q.m + 1) + 8 * q.n + 8 * q.m * 6
 
 
@@ -471,7 +482,7 @@ def main():
     timed = sum(i["fam_timed"][f] for i in infos)
     ms = sum(i["fam_ms"][f] for i in infos)
     avg_us = 1e3 * ms / max(timed, 1)
-    nbytes = hp_bytes(q.n, q.nnz_Q)
+    nbytes = hp_bytes(q.n, q.nnz_Q, bound_bytes(q))
     # launches that found the inner solve already stopped return at once; their
     # time stays in the denominator, their bytes do not count
     launches = sum(i["fam_launches"][f] for i in infos)

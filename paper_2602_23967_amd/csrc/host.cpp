@@ -9,7 +9,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -344,6 +346,75 @@ int upload(qp_handle* h, T** p, const T* src, size_t count)
     return 0;
 }
 
+// The variable bounds as two BoundVec (pdhcg_internal.h): one pair shared
+// by every variable, a byte class per variable when at most 256 distinct
+// (l, u) pairs occur (compared bit for bit, so every value is kept
+// exactly), else the two arrays.  PDHCG_BOUND_STORAGE=arrays in the
+// environment forces the arrays (to check that every storage gives the
+// same bits).
+int upload_bounds(qp_handle* h, DevState& S, const std::vector<double>& lv, const std::vector<double>& uv)
+{
+    const size_t n = lv.size();
+    const char* force = std::getenv("PDHCG_BOUND_STORAGE");
+    const bool arrays_only = force && std::strcmp(force, "arrays") == 0;
+    typedef std::pair<uint64_t, uint64_t> Key;
+    std::map<Key, int> index;
+    std::vector<Key> keys;
+    std::vector<unsigned char> cls(n);
+    bool few = !arrays_only;
+    int last = -1;
+    Key lastkey{0, 0};
+    for (size_t i = 0; i < n && few; ++i) {
+        Key key;
+        std::memcpy(&key.first, &lv[i], sizeof(double));
+        std::memcpy(&key.second, &uv[i], sizeof(double));
+        if (last < 0 || key != lastkey) {
+            auto it = index.find(key);
+            if (it != index.end()) {
+                last = it->second;
+            } else {
+                if (keys.size() == 256) { few = false; break; }
+                last = (int)keys.size();
+                index.emplace(key, last);
+                keys.push_back(key);
+            }
+            lastkey = key;
+        }
+        cls[i] = (unsigned char)last;
+    }
+    S.lv = BoundVec{};
+    S.uv = BoundVec{};
+    int rc;
+    if (few && keys.size() == 1) {
+        S.lv.mode = S.uv.mode = 1;
+        S.lv.k = lv[0];
+        S.uv.k = uv[0];
+        return 0;
+    }
+    if (few) {
+        std::vector<double> tl(keys.size()), tu(keys.size());
+        for (size_t c = 0; c < keys.size(); ++c) {
+            std::memcpy(&tl[c], &keys[c].first, sizeof(double));
+            std::memcpy(&tu[c], &keys[c].second, sizeof(double));
+        }
+        unsigned char* dc = nullptr;
+        double *dl = nullptr, *du = nullptr;
+        if ((rc = upload(h, &dc, cls.data(), n)) || (rc = upload(h, &dl, tl.data(), tl.size())) ||
+            (rc = upload(h, &du, tu.data(), tu.size())))
+            return rc;
+        S.lv.mode = S.uv.mode = 2;
+        S.lv.cls = S.uv.cls = dc;
+        S.lv.tab = dl;
+        S.uv.tab = du;
+        return 0;
+    }
+    double *dl = nullptr, *du = nullptr;
+    if ((rc = upload(h, &dl, lv.data(), n)) || (rc = upload(h, &du, uv.data(), n))) return rc;
+    S.lv.a = dl;
+    S.uv.a = du;
+    return 0;
+}
+
 int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_t* rp,
                const int32_t* cj, const double* v)
 {
@@ -548,8 +619,7 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     for (int64_t i = 0; i < m; ++i) { lcv[i] = lc[i]; ucv[i] = uc[i]; }
     if ((rc = upload(h, &S.qd, qd.data(), n))) return bail(rc);
     if ((rc = upload(h, &S.c, c, n))) return bail(rc);
-    if ((rc = upload(h, &S.lv, lvv.data(), n))) return bail(rc);
-    if ((rc = upload(h, &S.uv, uvv.data(), n))) return bail(rc);
+    if ((rc = upload_bounds(h, S, lvv, uvv))) return bail(rc);
     if ((rc = upload(h, &S.lc, lcv.data(), m))) return bail(rc);
     if ((rc = upload(h, &S.uc, ucv.data(), m))) return bail(rc);
     double** nvecs[] = {&S.x, &S.xa, &S.rhs, &S.g, &S.hp, &S.aty, &S.xbar};

@@ -334,7 +334,8 @@ __device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long lo
 // the movement ||x_T - x||^2 and, when a check follows, the pieces of the
 // unboundedness certificate d = proj_Recc(X)(x_T - x) (Section 5).
 struct HalpernX {
-    const double *xa, *c, *lv, *uv;
+    const double *xa, *c;
+    BoundVec lv, uv;
     double *x, *d;
     int store;
     double w, wa, th;
@@ -379,7 +380,8 @@ struct HalpernX {
 struct EpiProx : EpiBase {
     static constexpr bool BULK = true;
     static constexpr int NR = 3;
-    const double *y, *c, *qd, *lv, *uv;
+    const double *y, *c, *qd;
+    BoundVec lv, uv;
     double *x, *xt, *xbar;
     HalpernX hx;
     // mixed precision: A' y = A' y_ref + A'(y - y_ref) (dy32, aty_ref), and
@@ -436,7 +438,7 @@ struct EpiXbar : EpiBase {
 // x <- clip(x, l_v, u_v)
 struct EpiClip : EpiBase {
     static constexpr int NR = 0;
-    const double *lv, *uv;
+    BoundVec lv, uv;
     double* x;
     __device__ void elem(long long i, Acc<NR>) const { x[i] = clampd(x[i], lv[i], uv[i]); }
 };
@@ -465,7 +467,8 @@ struct EpiRhs : EpiBase {
 struct EpiRhsGrad : EpiBase {
     static constexpr bool BULK = true;
     static constexpr int NR = 3;
-    const double *y, *x, *c, *xt, *lv, *uv;
+    const double *y, *x, *c, *xt;
+    BoundVec lv, uv;
     double *rhs, *g;
     unsigned long long* dstat;
     long long seq;
@@ -513,7 +516,8 @@ struct EpiRhsGrad : EpiBase {
 struct EpiGinit : EpiBase {
     static constexpr int NR = 3;   // the exact gradient: FP64 in every precision
     const double* xt;
-    const double *rhs, *lv, *uv;
+    const double* rhs;
+    BoundVec lv, uv;
     double* g;
     unsigned long long* dstat;
     long long seq;
@@ -550,7 +554,8 @@ struct EpiGinit : EpiBase {
 struct EpiStepA : EpiBase {
     static constexpr bool BULK = true;
     static constexpr int NR = 4;
-    const double *p, *lv, *uv, *rhs;
+    const double *p, *rhs;
+    BoundVec lv, uv;
     double *xt, *g, *hp;
     unsigned long long* dstat;
     double it, abar;
@@ -624,7 +629,8 @@ struct EpiStepA : EpiBase {
 // adds the projected step x <- clip(x - abar phi(x)) and asks for a fresh g
 struct EpiStepB : EpiBase {
     static constexpr int NR = 4;
-    const double *p, *hp, *lv, *uv;
+    const double *p, *hp;
+    BoundVec lv, uv;
     double *xt, *g;
     unsigned long long* dstat;
     double alpha, abar;
@@ -669,7 +675,8 @@ struct EpiStepB : EpiBase {
 // next direction: beta (proportioning), phi, or phi - gam p (conjugate)
 struct EpiDir : EpiBase {
     static constexpr int NR = 0;
-    const double *xt, *g, *lv, *uv;
+    const double *xt, *g;
+    BoundVec lv, uv;
     double* p;
     double gam, abar;
     int mode;
@@ -784,7 +791,8 @@ struct EpiTailHp : EpiBase {
 // w = A' ytil: violation of A'ytil in R and p(-proj_R(A'ytil); l_v, u_v)
 struct EpiPinf : EpiBase {
     static constexpr int NR = 3;
-    const double *ytil, *lv, *uv;
+    const double* ytil;
+    BoundVec lv, uv;
     __device__ static int kind(int j) { return j == 0 ? R_MAX : R_SUM; }
     __device__ double xval(int j) const { return ytil[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
@@ -891,7 +899,8 @@ __device__ bool dual_infeasible(const Ctrl* c)
 // finalize makes the termination / infeasibility / restart decision
 struct EpiQx : EpiBase {
     static constexpr int NR = 7;
-    const double *x, *xa, *c, *aty, *lv, *uv;
+    const double *x, *xa, *c, *aty;
+    BoundVec lv, uv;
     unsigned long long* dcheck;
     int full;
     __device__ static int kind(int j) { return (j == 0 || j == 1 || j == 5) ? R_MAX : R_SUM; }
@@ -1039,7 +1048,7 @@ struct EpiRefZero : EpiBase {
 // start point x0 = proj_X(0), y0 = 0, anchors and T(z) set to the start
 struct EpiStart : EpiBase {
     static constexpr int NR = 0;
-    const double *lv, *uv;
+    BoundVec lv, uv;
     double *x, *xa, *xt, *y, *ya, *yt;
     int n;
     __device__ void elem(long long i, Acc<NR>) const

@@ -109,6 +109,23 @@ struct Ctrl {
     double pw_norm;
 };
 
+// One side (lower or upper) of the variables' box.  Most problems share a
+// few (l, u) pairs among all variables, so the bounds are kept as one
+// constant (mode 1), a byte class per variable into a table of at most 256
+// values (mode 2), or an array (mode 0): the inner steps then read one byte
+// or nothing per variable instead of 16 bytes.  Exact: the same values.
+struct BoundVec {
+    const double* a = nullptr;            // mode 0: per variable
+    const unsigned char* cls = nullptr;   // mode 2: class of each variable
+    const double* tab = nullptr;          // mode 2: value of each class
+    double k = 0.0;                       // mode 1: the value
+    int mode = 0;
+    __device__ __forceinline__ double operator[](long long i) const
+    {
+        return mode == 1 ? k : (mode == 2 ? tab[cls[i]] : a[i]);
+    }
+};
+
 struct DevState {
     int n = 0, m = 0;
     CsrDev Q, A, AT;
@@ -118,7 +135,8 @@ struct DevState {
     int k = 0;
     int qdiag = 0;                 // Q diagonal (closed-form primal step)
     double* qd = nullptr;          // diagonal of Q (n)
-    double *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
+    double *c = nullptr, *lc = nullptr, *uc = nullptr;
+    BoundVec lv, uv;               // variable bounds (n)
     // iterates
     double *x = nullptr, *y = nullptr, *xa = nullptr, *ya = nullptr, *xt = nullptr, *yt = nullptr;
     // work vectors

@@ -384,3 +384,24 @@ def test_graph_inner_steps_match_eager(torch, make):
                 assert g.info["iterations"] == ref.info["iterations"]
                 assert g.info["inner_iterations"] == ref.info["inner_iterations"]
                 assert np.array_equal(g.x, ref.x) and np.array_equal(g.y, ref.y)
+
+
+@pytest.mark.parametrize("make", [lambda: I.random_small(1),                 # one (l, u) pair
+                                  lambda: I.mixed_bounds(0),                 # class table
+                                  lambda: I.portfolio(1, n_assets=20000, k_factors=100),
+                                  lambda: I.mixed_bounds(1, n=1200, m=400)])  # > 256 pairs: arrays
+def test_bound_storage_gives_the_same_bits(torch, make, monkeypatch):
+    """The box is stored as one pair, a byte class per variable, or arrays,
+    whichever is smallest; every storage must give the same result bit for
+    bit as the arrays."""
+    q = make()
+    g = _gpu_solve(q)
+    monkeypatch.setenv("PDHCG_BOUND_STORAGE", "arrays")
+    a = _gpu_solve(q)
+    print(f"{q.name}: {g.info['iterations']}/{g.info['inner_iterations']} iterations, "
+          f"{g.info['solve_seconds'] * 1e3:.1f} ms vs {a.info['solve_seconds'] * 1e3:.1f} ms with arrays")
+    assert g.status == a.status == P.OPTIMAL
+    assert g.info["iterations"] == a.info["iterations"]
+    assert g.info["inner_iterations"] == a.info["inner_iterations"]
+    assert np.array_equal(g.x, a.x) and np.array_equal(g.y, a.y)
+    _assert_kkt(q, g)
