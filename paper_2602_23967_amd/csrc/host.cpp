@@ -455,14 +455,23 @@ int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_
     M.nblk = (int)blk.size();
     if ((rc = upload(h, &M.blk, blk.data(), blk.size()))) return rc;
     if ((rc = dalloc(h, &M.seg_part, (size_t)std::max(nseg, 1)))) return rc;
+    // long rows: those the finishing kernel sums with the whole block first
+    // (all when they are few, else the ones with many segments), then the
+    // rest, each group in row order
     std::vector<int> info;
-    for (const BlkDesc& b : blk)
-        if (b.nrows == 0 && b.nseg > 0 && b.seg == 0) {
-            info.push_back(b.row0);
-            info.push_back(b.seg_base);
-            info.push_back(b.nseg);
-        }
+    int ncoop = 0;
+    for (int pass = 0; pass < 2; ++pass)
+        for (const BlkDesc& b : blk)
+            if (b.nrows == 0 && b.nseg > 0 && b.seg == 0) {
+                const bool coop = nlr <= LR_COOP || b.nseg > LR_SEG_SERIAL;
+                if (coop != (pass == 0)) continue;
+                info.push_back(b.row0);
+                info.push_back(b.seg_base);
+                info.push_back(b.nseg);
+                ncoop += coop ? 1 : 0;
+            }
     M.nlr = nlr;
+    M.nlr_coop = ncoop;
     if ((rc = upload(h, &M.lr_info, info.data(), info.size()))) return rc;
     return 0;
 }

@@ -195,9 +195,35 @@ __global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
     }
 }
 
-// long rows up to which the finishing kernel completes each row with the
-// whole block (beyond: one thread per row)
-constexpr int LR_COOP = 32;
+// The finishing kernels run E::finalize (the method's scalar control logic)
+// on a copy of the control block in LDS: the block reads it with one wide
+// parallel load while the partials are summed, thread 0 then takes its
+// decisions against LDS instead of a chain of dependent global loads, and
+// the block writes the copy back.
+constexpr int CTRL_WORDS = (int)(sizeof(Ctrl) / 8);
+static_assert(sizeof(Ctrl) % 8 == 0, "Ctrl is copied as 64-bit words");
+
+__device__ __forceinline__ void ctrl_to_lds(const Ctrl* g, unsigned long long* s)
+{
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(g);
+    for (int i = threadIdx.x; i < CTRL_WORDS; i += blockDim.x) s[i] = src[i];
+}
+
+// after a barrier that follows ctrl_to_lds: finalize on the copy (thread 0),
+// then every thread writes its words back
+template <class E>
+__device__ __forceinline__ void finalize_in_lds(const E& e, const double* acc, unsigned long long* s)
+{
+    if (threadIdx.x == 0) {
+        E el = e;
+        el.ctrl = reinterpret_cast<Ctrl*>(s);
+        el.finalize(acc);
+    }
+    __syncthreads();
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(e.ctrl);
+    for (int i = threadIdx.x; i < CTRL_WORDS; i += blockDim.x) dst[i] = s[i];
+}
+
 
 // one block: completes the long rows (their segment partials summed by a
 // fixed tree, or in segment order when there are many long rows), sums
@@ -207,17 +233,20 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double lds[NR * (FIN_T / 64)];
+    __shared__ unsigned long long sctrl[CTRL_WORDS];
     E e = epi;
     if (e.skip()) return;
     e.init();
+    if constexpr (E::NR > 0) ctrl_to_lds(e.ctrl, sctrl);
     double acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
-    if (M.nlr <= LR_COOP) {
-        // few long rows (a budget row, a dense column): the whole block sums
-        // each one's segment partials (fixed tree order)
+    {
+        // long rows with many segments (a budget row, a dense column), or
+        // all of them when they are few: the whole block sums each one's
+        // segment partials (fixed tree order)
         __shared__ double lds1[FIN_T / 64];
-        for (int lr = 0; lr < M.nlr; ++lr) {
+        for (int lr = 0; lr < M.nlr_coop; ++lr) {
             const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
             double part[1] = {0.0};
             for (int i = threadIdx.x; i < nseg; i += FIN_T) part[0] += M.seg_part[base + i];
@@ -228,8 +257,10 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
                 e.row(row, total, acc);
             }
         }
-    } else {
-        for (int lr = threadIdx.x; lr < M.nlr; lr += FIN_T) {
+    }
+    {
+        // the rest: one thread per row (few segments each), in segment order
+        for (int lr = M.nlr_coop + threadIdx.x; lr < M.nlr; lr += FIN_T) {
             const int row = M.lr_info[3 * lr], base = M.lr_info[3 * lr + 1], nseg = M.lr_info[3 * lr + 2];
             double total = 0.0;
             for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
@@ -244,7 +275,7 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
             for (int j = 0; j < NR; ++j) acc[j] = rcomb(E::kind(j), acc[j], partials[(size_t)b * NR + j]);
         }
         block_reduce<E, FIN_T>(acc, lds);
-        if (threadIdx.x == 0) e.finalize(acc);
+        finalize_in_lds(e, acc, sctrl);
     }
 }
 
@@ -275,9 +306,11 @@ __global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double lds[NR * (FIN_T / 64)];
+    __shared__ unsigned long long sctrl[CTRL_WORDS];
     E e = epi;
     if (e.skip()) return;
     e.init();
+    ctrl_to_lds(e.ctrl, sctrl);
     double acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
@@ -287,7 +320,7 @@ __global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double
         for (int j = 0; j < NR; ++j) acc[j] = rcomb(E::kind(j), acc[j], partials[(size_t)b * NR + j]);
     }
     block_reduce<E, FIN_T>(acc, lds);
-    if (threadIdx.x == 0) e.finalize(acc);
+    finalize_in_lds(e, acc, sctrl);
 }
 
 // ---------------------------------------------------------------------------

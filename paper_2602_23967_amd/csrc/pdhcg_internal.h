@@ -30,6 +30,11 @@ constexpr int NPARTS = PDHCG_NPARTS;
 constexpr int PART_MIN_COLS = 262144;
 constexpr int PART_ROWS_CAP = PDHCG_PART_ROWS_CAP;   // rows per block of a column part
 constexpr int FIN_T = 1024;     // threads of the one-block finishing kernels
+// long rows the finishing kernel completes with the whole block: all of them
+// when there are at most LR_COOP, else those with more than LR_SEG_SERIAL
+// segments (the others one thread per row)
+constexpr int LR_COOP = 32;
+constexpr int LR_SEG_SERIAL = 8;
 
 // One work item of the row-block SpMV schedule.
 //   nrows > 0            rows [row0, row0+nrows), nonzeros [k0, k1); for a
@@ -57,6 +62,7 @@ struct CsrDev {
     double* seg_part = nullptr;
     int* lr_info = nullptr;    // per long row: {row, first segment slot, segment count}
     int nlr = 0;
+    int nlr_coop = 0;          // the first nlr_coop long rows are summed by the whole block
 };
 
 // inner-solver direction kinds
