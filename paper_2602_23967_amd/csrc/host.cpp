@@ -645,7 +645,8 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     if ((rc = dalloc(h, &S.v2, nm))) return bail(rc);
     if ((rc = dalloc(h, &S.ctrl, 1))) return bail(rc);
     const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, S.R.nblk, VEC_GRID_MAX});   // partials slots
-    if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8))) return bail(rc);
+    if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8 * 2))) return bail(rc);
+    S.partials2 = S.partials + (size_t)maxblk * 8;
     if (hipMemsetAsync(S.ctrl, 0, sizeof(Ctrl), h->own) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemset failed"));
 
@@ -1086,7 +1087,8 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
         }
         {
             Timed t(h, QP_FAM_DUAL);
-            HIPCHK(launch_dual(S, next_check, s));
+            const int pre = S.qdiag ? (prox_diag_deferrable(S) ? PRE_PROX : PRE_NONE) : PRE_XBAR;
+            HIPCHK(launch_dual(S, next_check, pre, s));
         }
         ++k;
     }

@@ -228,8 +228,47 @@ __device__ __forceinline__ void finalize_in_lds(const E& e, const double* acc, u
 // one block: completes the long rows (their segment partials summed by a
 // fixed tree, or in segment order when there are many long rows), sums
 // the per-block partials in block order, and runs the epilogue's finalize
-template <class E>
-__global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const double* partials)
+// An earlier epilogue's finishing step carried into this finishing kernel
+// (its partials were kept in their own slots): used when no kernel between
+// the two launches reads what that finalize writes, saving one launch.
+struct NoPre {
+    static constexpr int NR = 0;
+    Ctrl* ctrl;
+    __device__ static int kind(int) { return R_SUM; }
+    __device__ void init() {}
+    __device__ void finalize(const double*) const {}
+};
+
+template <class Pre>
+__device__ __forceinline__ void finish_pre(const Pre& pre, int nblk, const double* partials,
+                                           unsigned long long* sctrl)
+{
+    if constexpr (Pre::NR > 0) {
+        __shared__ double ldsp[Pre::NR * (FIN_T / 64)];
+        double acc[Pre::NR];
+#pragma unroll
+        for (int j = 0; j < Pre::NR; ++j) acc[j] = rid(Pre::kind(j));
+#pragma unroll 4
+        for (int b = threadIdx.x; b < nblk; b += FIN_T) {
+#pragma unroll
+            for (int j = 0; j < Pre::NR; ++j) acc[j] = rcomb(Pre::kind(j), acc[j], partials[(size_t)b * Pre::NR + j]);
+        }
+        block_reduce<Pre, FIN_T>(acc, ldsp);
+        if (threadIdx.x == 0) {
+            // init reads the control values the epilogue's own kernel saw
+            // (nothing has changed them since)
+            Pre el = pre;
+            el.ctrl = reinterpret_cast<Ctrl*>(sctrl);
+            el.init();
+            el.finalize(acc);
+        }
+        __syncthreads();
+    }
+}
+
+template <class E, class Pre = NoPre>
+__global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const double* partials, Pre pre = Pre{},
+                                                    int pre_nblk = 0, const double* pre_partials = nullptr)
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double lds[NR * (FIN_T / 64)];
@@ -237,7 +276,10 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
     E e = epi;
     if (e.skip()) return;
     e.init();
-    if constexpr (E::NR > 0) ctrl_to_lds(e.ctrl, sctrl);
+    if constexpr (E::NR > 0) {
+        ctrl_to_lds(e.ctrl, sctrl);
+        finish_pre(pre, pre_nblk, pre_partials, sctrl);
+    }
     double acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
@@ -301,8 +343,9 @@ __global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* parti
     }
 }
 
-template <class E>
-__global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double* partials)
+template <class E, class Pre = NoPre>
+__global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double* partials, Pre pre = Pre{},
+                                                   int pre_nblk = 0, const double* pre_partials = nullptr)
 {
     constexpr int NR = E::NR > 0 ? E::NR : 1;
     __shared__ double lds[NR * (FIN_T / 64)];
@@ -311,6 +354,7 @@ __global__ __launch_bounds__(FIN_T) void k_vec_fin(int nblk, E epi, const double
     if (e.skip()) return;
     e.init();
     ctrl_to_lds(e.ctrl, sctrl);
+    finish_pre(pre, pre_nblk, pre_partials, sctrl);
     double acc[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
@@ -1177,33 +1221,45 @@ static void launch_spmv_main(const CsrDev& M, const E& e, double* partials, hipS
     k_spmv<E, false><<<M.nblk, TPB, 0, s>>>(M, e, partials);
 }
 
-template <class E>
-static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s)
+// blocks whose partials a product leaves for its finishing step
+static int spmv_partial_blocks(const CsrDev& M) { return M.nparts > 1 ? vec_grid(M.rows) : M.nblk; }
+
+// Product with epilogue e.  defer: leave e's partials in S.partials2 and
+// launch no finishing kernel (the caller hands e to the next product's
+// finishing kernel as `pre`; only valid when the product has no long rows
+// to complete).  pre / pre_nblk: an earlier deferred epilogue finished first.
+template <class E, class Pre = NoPre>
+static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s, bool defer = false,
+                           const Pre& pre = Pre{}, int pre_nblk = 0)
 {
+    double* part = defer ? S.partials2 : S.partials;
     if (M.nparts > 1) {
         const int grid = vec_grid(M.rows);
         if (S.tev) (void)hipEventRecord(S.tev[0], s);
-        launch_spmv_main(M, e, S.partials, s);
-        k_rows<E><<<grid, TPB, 0, s>>>(M, e, S.partials);
+        launch_spmv_main(M, e, part, s);
+        k_rows<E><<<grid, TPB, 0, s>>>(M, e, part);
         if (S.tev) (void)hipEventRecord(S.tev[1], s);
-        if (E::NR > 0) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, S.partials);
+        if (E::NR > 0 && !defer)
+            k_vec_fin<E, Pre><<<1, FIN_T, 0, s>>>(grid, e, part, pre, pre_nblk, S.partials2);
         return hipGetLastError();
     }
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
-    launch_spmv_main(M, e, S.partials, s);
+    launch_spmv_main(M, e, part, s);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
-    if (E::NR > 0 || M.nlr > 0) k_spmv_fin<E><<<1, FIN_T, 0, s>>>(M, e, S.partials);
+    if ((E::NR > 0 || M.nlr > 0) && !defer)
+        k_spmv_fin<E, Pre><<<1, FIN_T, 0, s>>>(M, e, part, pre, pre_nblk, S.partials2);
     return hipGetLastError();
 }
 
 template <class E>
-static hipError_t run_vec(const DevState& S, long long len, const E& e, hipStream_t s)
+static hipError_t run_vec(const DevState& S, long long len, const E& e, hipStream_t s, bool defer = false)
 {
     const int grid = vec_grid(len);
+    double* part = defer ? S.partials2 : S.partials;
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
-    k_vec<E><<<grid, TPB, 0, s>>>(len, e, S.partials);
+    k_vec<E><<<grid, TPB, 0, s>>>(len, e, part);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
-    if (E::NR > 0) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, S.partials);
+    if (E::NR > 0 && !defer) k_vec_fin<E><<<1, FIN_T, 0, s>>>(grid, e, part);
     return hipGetLastError();
 }
 
@@ -1225,7 +1281,7 @@ static HalpernX halpern_x(const DevState& S, int store_delta)
     return h;
 }
 
-hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s)
+static EpiProx prox_epi(const DevState& S, int store_delta)
 {
     EpiProx e{};
     e.ctrl = S.ctrl;
@@ -1233,7 +1289,18 @@ hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s)
     e.xbar = S.xbar;
     e.hx = halpern_x(S, store_delta);
     if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; e.xref = S.xref; e.dxb32 = S.dxb32; }
-    return run_spmv(S, S.AT, e, s);
+    return e;
+}
+
+// The primal step's finishing work (the movement of x and, before a check,
+// the unboundedness pieces, and the inner tolerance) feeds nothing the dual
+// step reads, so it is carried into the dual step's finishing kernel when
+// the product has no long rows to complete there.
+bool prox_diag_deferrable(const DevState& S) { return S.AT.nlr == 0; }
+
+hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s)
+{
+    return run_spmv(S, S.AT, prox_epi(S, store_delta), s, prox_diag_deferrable(S));
 }
 
 hipError_t launch_rhs(const DevState& S, hipStream_t s)
@@ -1316,14 +1383,22 @@ hipError_t launch_update(const DevState& S, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s)
+static EpiXbar xbar_epi(const DevState& S, int store_delta)
 {
     EpiXbar e{};
     e.ctrl = S.ctrl;
     e.xt = S.xt; e.xbar = S.xbar;
     e.hx = halpern_x(S, store_delta);
     if (S.mixed) { e.xref = S.xref; e.dxb32 = S.dxb32; }
-    return run_vec(S, S.n, e, s);
+    return e;
+}
+
+// x_bar and the Halpern average of x after an inner solve; its finishing
+// work is carried into the dual step's finishing kernel (as for the
+// closed-form primal step)
+hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s)
+{
+    return run_vec(S, S.n, xbar_epi(S, store_delta), s, true);
 }
 
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
@@ -1334,13 +1409,17 @@ hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s)
+hipError_t launch_dual(const DevState& S, int store_delta, int pre, hipStream_t s)
 {
     EpiDual e{};
     e.ctrl = S.ctrl;
     e.xbar = S.xbar; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
     if (S.mixed) { e.dxb32 = S.dxb32; e.axref = S.axref; e.yref = S.yref; e.dy32 = S.dy32; }
+    if (pre == PRE_PROX)
+        return run_spmv(S, S.A, e, s, false, prox_epi(S, store_delta), spmv_partial_blocks(S.AT));
+    if (pre == PRE_XBAR)
+        return run_spmv(S, S.A, e, s, false, xbar_epi(S, store_delta), vec_grid(S.n));
     return run_spmv(S, S.A, e, s);
 }
 

@@ -156,6 +156,7 @@ struct DevState {
     float *dxb32 = nullptr, *dy32 = nullptr;
     Ctrl* ctrl = nullptr;
     double* partials = nullptr;
+    double* partials2 = nullptr;   // partials of an epilogue whose finish is deferred
     hipEvent_t* tev = nullptr;             // when set: events around the next main kernel
     unsigned long long* dstat = nullptr;   // pinned status word (device view)
     unsigned long long* dcheck = nullptr;  // pinned check result (device view)
@@ -165,7 +166,10 @@ struct DevState {
 // Every launcher enqueues on `s` and returns hipGetLastError().
 hipError_t launch_init_start(const DevState& S, hipStream_t s);
 // closed-form primal step fused with x_bar and the Halpern average of x
+// the closed-form primal step; its finishing work is left for the dual
+// step's finishing kernel when prox_diag_deferrable(S)
 hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s);
+bool prox_diag_deferrable(const DevState& S);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
 // tail = R v for a factored Q (no-op otherwise); bulk: FP32 in mixed precision
@@ -177,9 +181,14 @@ hipError_t launch_dir(const DevState& S, hipStream_t s);
 hipError_t launch_hp(const DevState& S, hipStream_t s);
 hipError_t launch_update(const DevState& S, hipStream_t s);
 // x_bar = 2 x_T - x fused with the Halpern average of x
+// x_bar and Halpern on x; its finishing work is always left for the dual
+// step's finishing kernel (launch_dual with PRE_XBAR)
 hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s);
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- proj_X(x)
-hipError_t launch_dual(const DevState& S, int store_delta, hipStream_t s);
+// dual step and Halpern on y; pre names the earlier epilogue whose finishing
+// work its finishing kernel runs first (same store_delta)
+enum { PRE_NONE = 0, PRE_PROX = 1, PRE_XBAR = 2 };
+hipError_t launch_dual(const DevState& S, int store_delta, int pre, hipStream_t s);
 // KKT pieces at (x, y); with `full` also the infeasibility certificates
 // (and, with `dinf`, the unboundedness ones) and the solver's decision
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
