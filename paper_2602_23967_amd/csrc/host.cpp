@@ -421,7 +421,7 @@ int upload_csr(qp_handle* h, CsrDev& M, int64_t rows, int64_t cols, const int64_
     M.rows = (int)rows;
     M.cols = (int)cols;
     M.nnz = rp ? rp[rows] : 0;
-    if (rp && cols >= PART_MIN_COLS && rows > 0 && M.nnz > 0) {
+    if (rp && cols >= PART_MIN_COLS && rows > 0 && M.nnz > 0 && M.nnz >= (int64_t)PART_MIN_NNZ_ROW * rows) {
         std::vector<int> prow;
         std::vector<int32_t> pcol;
         std::vector<double> pval;

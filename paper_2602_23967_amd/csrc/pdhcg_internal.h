@@ -21,13 +21,25 @@ constexpr int VEC_GRID_MAX = 2048;
 // doubles is split into NPARTS contiguous column parts; block b of the
 // product works on part b % NPARTS, which on gfx950's round-robin dispatch of
 // blocks to its 8 XCDs keeps each XCD's gathers inside one part (1/4 of the
-// operand, L2-resident).  4 parts measured faster than 8 (half the partial
-// row traffic, gathers still L2 hits).
+// operand, L2-resident).  4 parts measured faster than 2 or 8 on the
+// 1e6 x 1e6 product with 11 nonzeros per row (71 us against 77 and 101:
+// 2 parts' 4 MB segments thrash the 4 MB L2, 8 parts double the partial row
+// traffic); the gathers themselves reach about 250 G/s with 2 to 16 parts
+// and 120 G/s with none.
 #ifndef PDHCG_NPARTS
 #define PDHCG_NPARTS 4
 #endif
 constexpr int NPARTS = PDHCG_NPARTS;
 constexpr int PART_MIN_COLS = 262144;
+// and with at least this many nonzeros per row on average: a part of a
+// sparser matrix holds about one nonzero per row, and the partial row sums
+// (NPARTS x 8 bytes per row, written and read back) cost more than the
+// gathers save (A' of the large sparse QP, 4 per row: 49 us whole against
+// 62 us in parts; A, 8 per row: 55 us in parts against 59 us whole)
+#ifndef PDHCG_PART_MIN_NNZ_ROW
+#define PDHCG_PART_MIN_NNZ_ROW 6
+#endif
+constexpr int PART_MIN_NNZ_ROW = PDHCG_PART_MIN_NNZ_ROW;
 constexpr int PART_ROWS_CAP = PDHCG_PART_ROWS_CAP;   // rows per block of a column part
 constexpr int FIN_T = 1024;     // threads of the one-block finishing kernels
 // long rows the finishing kernel completes with the whole block: all of them
