@@ -362,7 +362,8 @@ def main_serve(args, torch, P, I):
         "dtype": "f32 products + f64" if mixed else "f64", "data": "synthetic",
         "config": {"workload": f"served stream: {len(qs)} requests, Poisson arrivals at {args.rate:g}/s, "
                                f"60% MPC / 30% random QP n~U(1e3,5e4) / 10% portfolio n~U(1e4,1e5), "
-                               f"2% infeasible, tol {args.tol:g}", **cfg},
+                               f"2% infeasible, tol {args.tol:g}", **cfg,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "solved": int(np.sum(ok)), "requests": len(qs),
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "per_kind": per_kind},
@@ -404,6 +405,10 @@ def main():
                     help="batched launch schedule: auto (autotuner), default, or SHAPE,ORDER")
     ap.add_argument("--batch-shape", type=int, default=-1, help="server batched launch shape (-1: default)")
     ap.add_argument("--batch-order", type=int, default=-1, help="server batched queue order (-1: default)")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="served stream: HIP hardware queues of the process (GPU_MAX_HW_QUEUES, set before "
+                         "the first HIP call when not already set; 0 keeps the runtime's default of 4, "
+                         "which measured faster than 16 on the served stream); at most 32")
     ap.add_argument("--one-at-a-time", type=int, default=32,
                     help="instances of the batched workload also solved one by one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -416,6 +421,9 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve" and args.hw_queues > 0 and "GPU_MAX_HW_QUEUES" not in os.environ:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
 
     import torch
 
