@@ -225,9 +225,6 @@ __device__ __forceinline__ void finalize_in_lds(const E& e, const double* acc, u
 }
 
 
-// one block: completes the long rows (their segment partials summed by a
-// fixed tree, or in segment order when there are many long rows), sums
-// the per-block partials in block order, and runs the epilogue's finalize
 // An earlier epilogue's finishing step carried into this finishing kernel
 // (its partials were kept in their own slots): used when no kernel between
 // the two launches reads what that finalize writes, saving one launch.
@@ -266,6 +263,10 @@ __device__ __forceinline__ void finish_pre(const Pre& pre, int nblk, const doubl
     }
 }
 
+// one block: runs a carried epilogue's finishing step, completes the long
+// rows (their segment partials summed by a fixed tree, or in segment order
+// for rows of few segments), sums the per-block partials in block order,
+// and runs the epilogue's finalize
 template <class E, class Pre = NoPre>
 __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const double* partials, Pre pre = Pre{},
                                                     int pre_nblk = 0, const double* pre_partials = nullptr)
