@@ -290,9 +290,13 @@ void qp_batch_destroy(qp_batch* bt);
 /* Number of compiled shapes, and shape i's threads per workgroup, LDS
  * doubles and the waves per SIMD its register allocation leaves room for
  * (1: as many registers as the workgroup size allows; more: fewer registers,
- * some spilled, more instances resident) (host outputs, may be NULL).  The
- * default shape is 1. */
+ * some spilled, more instances resident) (host outputs, may be NULL).  A new
+ * batch uses qp_batch_default_shape(0) whatever its instances, so that an
+ * instance's result never depends on the others in the batch;
+ * qp_batch_default_shape(1) is the shape that suits instances with an inner
+ * solve (non-diagonal Q) better, which the server's general lanes use. */
 int qp_batch_num_shapes(void);
+int qp_batch_default_shape(int32_t general);
 int qp_batch_shape_info(int32_t shape, int32_t* threads, int32_t* lds_doubles, int32_t* waves_per_simd);
 
 /* Set the schedule of later solves of bt (-1 keeps a field); get it. */
@@ -336,9 +340,12 @@ typedef struct {
     int32_t general_lanes;    /* batched launches in flight for non-diagonal-Q requests; 2 */
     int32_t single_workers;   /* single-path solves in flight; 8 */
     int32_t max_batch;        /* instances per batched launch; 1024 */
-    int32_t batch_shape;      /* launch shape of the batched launches (qp_batch_set_schedule),
-                                 -1: the library default */
+    int32_t batch_shape;      /* launch shape of the batched launches of diagonal-Q requests
+                                 (qp_batch_set_schedule), -1: the library default */
     int32_t batch_order;      /* their queue order (0 or 1), -1: the library default */
+    int32_t general_shape;    /* launch shape of the batched launches of non-diagonal-Q
+                                 requests, -1: qp_batch_default_shape(1) */
+    int32_t pad;
     double batch_linger_us;   /* a free lane waits up to this long (from the oldest waiting
                                  request's arrival) for more requests before launching; 200 */
 } qp_server_config;

@@ -73,6 +73,7 @@ class ServerConfig(C.Structure):
                 ("batch_lanes", C.c_int32), ("general_lanes", C.c_int32),
                 ("single_workers", C.c_int32), ("max_batch", C.c_int32),
                 ("batch_shape", C.c_int32), ("batch_order", C.c_int32),
+                ("general_shape", C.c_int32), ("pad", C.c_int32),
                 ("batch_linger_us", C.c_double)]
 
 
@@ -131,6 +132,7 @@ def lib():
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
         L.qp_batch_num_shapes.argtypes = []
+        L.qp_batch_default_shape.argtypes = [C.c_int32]
         L.qp_batch_shape_info.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]
         L.qp_batch_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
@@ -395,6 +397,11 @@ def qp_batch_destroy(h):
 
 def qp_batch_num_shapes() -> int:
     return _check(lib().qp_batch_num_shapes())
+
+
+def qp_batch_default_shape(general: bool = False) -> int:
+    """Default launch shape of a batch (general: the one for non-diagonal-Q instances)."""
+    return _check(lib().qp_batch_default_shape(1 if general else 0))
 
 
 def qp_batch_shape_info(shape):

@@ -1664,6 +1664,11 @@ int qp_batch_num_shapes(void)
     return count;
 }
 
+int qp_batch_default_shape(int32_t general)
+{
+    return general ? pdhcg::BATCH_SHAPE_GENERAL_DEFAULT : pdhcg::BATCH_SHAPE_DEFAULT;
+}
+
 int qp_batch_shape_info(int32_t shape, int32_t* threads, int32_t* lds_doubles, int32_t* waves_per_simd)
 {
     int count = 0;

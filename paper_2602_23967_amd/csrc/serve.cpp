@@ -160,7 +160,11 @@ int launch_lane(qp_server* s, Lane& L)
                           Ap.data(), Aj.data(), Av.data(), c.data(), b.data(), sense.data(), lb.data(),
                           ub.data(), &bt);
     if (rc) return rc;
-    rc = qp_batch_set_schedule(bt, s->cfg.batch_shape, s->cfg.batch_order);
+    // each lane class has its own launch shape (a request's result depends
+    // only on its class, never on the requests it shares a launch with)
+    const int shape = L.klass == 0 ? s->cfg.batch_shape
+                                   : (s->cfg.general_shape >= 0 ? s->cfg.general_shape : qp_batch_default_shape(1));
+    rc = qp_batch_set_schedule(bt, shape, s->cfg.batch_order);
     if (rc == 0) rc = batch_launch(bt, &s->params);
     if (rc) {
         qp_batch_destroy(bt);
@@ -333,6 +337,8 @@ qp_server_config qp_server_config_default(void)
     c.max_batch = 1024;
     c.batch_shape = -1;
     c.batch_order = -1;
+    c.general_shape = -1;
+    c.pad = 0;
     c.batch_linger_us = 200.0;
     return c;
 }
@@ -346,7 +352,8 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
     if (c.device_budget <= 0 || c.batch_max_dim < 0 || c.general_max_dim < 0 || c.batch_lanes < 0 ||
         c.general_lanes < 0 || c.single_workers < 0 || c.batch_lanes + c.general_lanes + c.single_workers < 1 ||
         c.max_batch < 1 || !(c.batch_linger_us >= 0.0) || c.batch_shape < -1 ||
-        c.batch_shape >= qp_batch_num_shapes() || c.batch_order < -1 || c.batch_order > 1)
+        c.batch_shape >= qp_batch_num_shapes() || c.batch_order < -1 || c.batch_order > 1 ||
+        c.general_shape < -1 || c.general_shape >= qp_batch_num_shapes())
         return fail(QP_ERR_INVALID_ARG, "invalid server configuration");
     if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 ||
         (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))

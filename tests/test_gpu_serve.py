@@ -45,9 +45,20 @@ def _submit_poisson(srv, qs, mean_gap_s, seed=0):
     return ids
 
 
+def _general(q):
+    import scipy.sparse as sp
+    if q.Q is None:
+        return False
+    r, c = sp.csr_matrix(q.Q).nonzero()
+    return bool(np.any(r != c))
+
+
 def _alone(q, params, route):
     if route == 0:
         with P.BatchSolver([q]) as bs:
+            # the server's general lanes use the shape for inner solves
+            if _general(q):
+                bs.set_schedule(P.qp_batch_default_shape(True), -1)
             bs.solve(params)
             return bs.result(0)
     with P.Solver(q) as s:
