@@ -386,15 +386,15 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 for (int j = tid; j < m; j += NT) yref[r0 + j] = yt[r0 + j];
             }
             wg_reduce<16, kinds, NT>(a, lds);
-            rp_ = a[4] / bscale;
+            rp_ = uniform(a[4] / bscale);
             double sd = a[9] > a[0] ? a[9] : a[0];
             sd = sd > cmax ? sd : cmax;
-            rd_ = a[8] / (1.0 + sd);
-            pobj = 0.5 * a[10] + a[11];
+            rd_ = uniform(a[8] / (1.0 + sd));
+            pobj = uniform(0.5 * a[10] + a[11]);
             const double dneg = 0.5 * a[10] + a[12] + a[5];
-            dobj = -dneg;
+            dobj = uniform(-dneg);
             const double den = fabs(pobj) > fabs(dneg) ? fabs(pobj) : fabs(dneg);
-            rg_ = fabs(a[10] + a[11] + a[12] + a[5]) / (1.0 + den);
+            rg_ = uniform(fabs(a[10] + a[11] + a[12] + a[5]) / (1.0 + den));
             double worst = rp_ > rd_ ? rp_ : rd_;
             worst = worst > rg_ ? worst : rg_;
             bool pinf = false, dinf = false;
@@ -418,23 +418,23 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 restart = R <= P.rs_suff * R_start ||
                           (R_prev_valid && R <= P.rs_nec * R_start && R > R_prev) ||
                           (double)t >= P.rs_art * (double)k;
-                R_prev = R;
+                R_prev = uniform(R);
                 R_prev_valid = 1;
                 if (restart) {
                     const double mx = sqrt(a[14]), my = sqrt(a[6]);
                     if (mx > 1e-10 && my > 1e-10 && isfinite(mx) && isfinite(my)) {
                         const double so = sqrt(omega);
                         const double e = log(so * mx / (my / so));
-                        pid_int += e;
+                        pid_int = uniform(pid_int + e);
                         double lw = log(omega) - (P.kp * e + P.ki * pid_int + P.kd * (e - pid_prev));
                         const double lo = log(omega0) - 10.0, hi = log(omega0) + 10.0;
                         lw = lw < lo ? lo : (lw > hi ? hi : lw);
-                        omega = exp(lw);
-                        pid_prev = e;
+                        omega = uniform(exp(lw));
+                        pid_prev = uniform(e);
                     }
-                    tau = eta / omega;
-                    sigma = eta * omega;
-                    it = 1.0 / tau;
+                    tau = uniform(eta / omega);
+                    sigma = uniform(eta * omega);
+                    it = uniform(1.0 / tau);
                     t = 0;
                     R_prev_valid = 0;
                     ++restarts;
@@ -495,7 +495,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 st[2] += sp.phit * sp.phi;
             }
             wg_reduce<3, 0u, NT>(st, lds);
-            if (isinf(eps) && P.eps_fixed <= 0.0) eps = fmax(P.gamma_inner * sqrt(st[0]), P.eps_min);
+            if (isinf(eps) && P.eps_fixed <= 0.0) eps = uniform(fmax(P.gamma_inner * sqrt(st[0]), P.eps_min));
             const double eps_use = P.eps_fixed > 0.0 ? P.eps_fixed : eps;
             long long inner = 0;
             int last = STEP_NONE;
@@ -628,17 +628,17 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             }
         }
         wg_reduce<7, kinds7, NT>(a, lds);
-        ndx2 = a[0];
-        ndy2 = a[1];
-        if (P.eps_fixed <= 0.0) eps = fmin(eps, fmax(P.gamma_inner * omega * sqrt(ndx2) / tau, P.eps_min));
+        ndx2 = uniform(a[0]);
+        ndy2 = uniform(a[1]);
+        if (P.eps_fixed <= 0.0) eps = uniform(fmin(eps, fmax(P.gamma_inner * omega * sqrt(ndx2) / tau, P.eps_min)));
         if (store) {
-            ytil_max = a[2]; ptil_sum = a[3]; ptil_abs = a[4];
-            d_max = unb ? a[5] : 0.0;
-            cd = unb ? a[6] : 0.0;
+            ytil_max = uniform(a[2]); ptil_sum = uniform(a[3]); ptil_abs = uniform(a[4]);
+            d_max = uniform(unb ? a[5] : 0.0);
+            cd = uniform(unb ? a[6] : 0.0);
         }
         ++k;
         ++t;
-        if (t == 1) R_start = sqrt(omega * ndx2 + ndy2 / omega);
+        if (t == 1) R_start = uniform(sqrt(omega * ndx2 + ndy2 / omega));
     }
     if (tid == 0) {
         BatchOut o;
