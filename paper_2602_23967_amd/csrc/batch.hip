@@ -307,6 +307,17 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
     double* sy = sbuf + n;
     double* sp_ = sbuf + n + m;
     double* sxt = sbuf + 2 * n + m;
+    // a closed-form instance small enough keeps its iterates in LDS for the
+    // whole solve as well: x, its anchor, x_T, y and its anchor (x_T is
+    // copied to HBM before each check, whose products read it there)
+    const int stage2 = uniform_int((!qgen && 4 * n + 3 * m <= LDSN) ? 1 : 0);
+    if (stage2) {
+        x = sbuf + n + m;
+        xa = x + n;
+        xt = xa + n;
+        y = xt + n;
+        ya = y + m;
+    }
     for (int i = tid; i < n; i += NT) {
         const double v = clampd(0.0, lv[i], uv[i]);
         x[i] = v; xa[i] = v; xt[i] = v;
@@ -328,6 +339,10 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
 
     for (;;) {
         if ((k > 0 || P.max_iter == 0) && (k % P.check_every == 0 || k >= P.max_iter)) {
+            if (stage2) {
+                for (int i = tid; i < n; i += NT) B.xt[v0 + i] = xt[i];
+                __syncthreads();
+            }
             // ---- check at (x_T, y_T): KKT pieces and certificate pieces ----------
             double a[16];
 #pragma unroll
@@ -467,7 +482,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
                 xt[i] = v;
                 const double xb = 2.0 * v - xi;
-                xbar[v0 + i] = xb;
+                if (!stage) xbar[v0 + i] = xb;   // staged: the dual step reads sx
                 if (stage) {
                     if constexpr (F32) sx[i] = xb - xref[v0 + i];
                     else sx[i] = xb;
@@ -577,7 +592,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             inner_total += inner;
             for (int i = tid; i < n; i += NT) {
                 const double xb = 2.0 * xt[i] - x[i];
-                xbar[v0 + i] = xb;
+                if (!stage) xbar[v0 + i] = xb;
                 if (stage) {
                     if constexpr (F32) sx[i] = xb - xref[v0 + i];
                     else sx[i] = xb;
@@ -599,7 +614,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             const double ytj = sigma * (v - clampd(v, l, u));
             const double dy = ytj - yj;
             a[1] += dy * dy;
-            yt[r0 + j] = ytj;
+            if (store) yt[r0 + j] = ytj;   // read only by the check that follows
             const double yn = P.use_halpern ? w * ((1.0 + th) * ytj - th * yj) + wa * ya[j] : ytj;
             y[j] = yn;
             if (stage) {
