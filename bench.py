@@ -94,11 +94,13 @@ def cpu_baseline(q, gpu_units_per_solve, sample_iters):
 
 def batch_bytes(q, iters, vb=12):
     """Algorithmic bytes of one instance's iterations in the batched kernel:
-    the A and A' products (vb B per nonzero each: 12 in FP64, 8 with FP32
-    values; int32 row pointers),
+    the A and A' products (vb B per nonzero each: the value, 8 in FP64 or 4
+    in FP32, and the column index, 2 when every instance is below 65536
+    variables and rows (16-bit local indices) else 4; int32 row pointers),
     the primal step (x, c, q, l_v, u_v read; x_T, x_bar written), the dual
     step (x_bar gathered once; y, y anchor, l_c, u_c read; y_T, y written)
-    and the Halpern step on x (x_T, x, anchor read; x written)."""
+    and the Halpern step on x (x_T, x, anchor read; x written) -- counted
+    as HBM traffic, as in the form that keeps no iterate on chip."""
     per_iter = 2 * vb * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * (7 + 1 + 4) + 8 * q.m * 6
     return per_iter * iters
 
@@ -148,7 +150,8 @@ def main_batch(args, torch, P, I):
     elapsed = time.perf_counter() - t_start
     infos = [bs.result(i).info for i in range(len(qs))]
     iters = [i["iterations"] for i in infos]
-    nbytes = sum(batch_bytes(q, it, 8 if mixed else 12) for q, it in zip(qs, iters))
+    col_b = 2 if max(max(q.n, q.m) for q in qs) <= 65536 else 4
+    nbytes = sum(batch_bytes(q, it, (4 if mixed else 8) + col_b) for q, it in zip(qs, iters))
     kernel_s = float(np.median(lat))
     bs.close()
     # the same instances one at a time through the single-QP path, FP64

@@ -87,11 +87,33 @@ __device__ void wg_reduce_min3(double (&v)[3], double* lds)
     __syncthreads();
 }
 
-__device__ __forceinline__ double row_dot(const int* rp, const int* col, const double* val,
-                                          const double* x, int row)
+// Column indices of a packed matrix: global 32-bit ones, or 16-bit indices
+// local to the instance (column = off + local), which cut the index bytes
+// of every product in half when every instance has fewer than 65536
+// variables and rows.  at(q, off) is the global column of entry q.
+template <bool C16>
+struct Cols {
+    const int* g;
+    const unsigned short* l;
+    __device__ __forceinline__ int at(int q, int off) const
+    {
+        if constexpr (C16) return off + (int)l[q];
+        else return g[q];
+    }
+    // the column relative to off (an index into an LDS copy of the operand)
+    __device__ __forceinline__ int rel(int q, int off) const
+    {
+        if constexpr (C16) return (int)l[q];
+        else return g[q] - off;
+    }
+};
+
+template <bool C16>
+__device__ __forceinline__ double row_dot(const int* rp, Cols<C16> col, const double* val,
+                                          const double* x, int row, int off)
 {
     double s = 0.0;
-    for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * x[col[q]];
+    for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * x[col.at(q, off)];
     return s;
 }
 
@@ -101,20 +123,20 @@ __device__ __forceinline__ double row_dot(const int* rp, const int* col, const d
 // ref + M (x - x_ref) with FP32 values, the difference rounded to FP32 and
 // an FP32 sum, so the FP32 rounding scales with the movement since the
 // check and not with the iterate.
-template <bool F32>
-__device__ __forceinline__ double row_dot_bulk(const int* rp, const int* col, const double* val,
+template <bool F32, bool C16>
+__device__ __forceinline__ double row_dot_bulk(const int* rp, Cols<C16> col, const double* val,
                                                const float* val32, const double* x, const double* xref,
-                                               double ref, int row)
+                                               double ref, int row, int off)
 {
     if constexpr (F32) {
         float s = 0.0f;
         for (int q = rp[row]; q < rp[row + 1]; ++q) {
-            const int j = col[q];
+            const int j = col.at(q, off);
             s += val32[q] * (float)(x[j] - xref[j]);
         }
         return ref + (double)s;
     } else {
-        return row_dot(rp, col, val, x, row);
+        return row_dot(rp, col, val, x, row, off);
     }
 }
 
@@ -127,18 +149,18 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
 // The same product with the operand staged in the workgroup's LDS (sv[j -
 // off] holds the operand, or in mixed precision its difference from the
 // reference point): identical arithmetic, LDS gathers instead of L2 ones.
-template <bool F32>
-__device__ __forceinline__ double row_dot_lds(const int* rp, const int* col, const double* val,
+template <bool F32, bool C16>
+__device__ __forceinline__ double row_dot_lds(const int* rp, Cols<C16> col, const double* val,
                                               const float* val32, const double* sv, int off, double ref,
                                               int row)
 {
     if constexpr (F32) {
         float s = 0.0f;
-        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)sv[col[q] - off];
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)sv[col.rel(q, off)];
         return ref + (double)s;
     } else {
         double s = 0.0;
-        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * sv[col[q] - off];
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val[q] * sv[col.rel(q, off)];
         return s;
     }
 }
@@ -146,16 +168,16 @@ __device__ __forceinline__ double row_dot_lds(const int* rp, const int* col, con
 // the inner step's product H p: FP32 values, direction and sum in mixed
 // precision (the inner solve re-forms its gradient in FP64 at every
 // subproblem and after every expansion step)
-template <bool F32>
-__device__ __forceinline__ double hp_dot(const int* rp, const int* col, const double* val,
-                                         const float* val32, const double* x, int row)
+template <bool F32, bool C16>
+__device__ __forceinline__ double hp_dot(const int* rp, Cols<C16> col, const double* val,
+                                         const float* val32, const double* x, int row, int off)
 {
     if constexpr (F32) {
         float s = 0.0f;
-        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)x[col[q]];
+        for (int q = rp[row]; q < rp[row + 1]; ++q) s += val32[q] * (float)x[col.at(q, off)];
         return (double)s;
     } else {
-        return row_dot(rp, col, val, x, row);
+        return row_dot(rp, col, val, x, row, off);
     }
 }
 
@@ -234,8 +256,8 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
         for (long long it = 1; it <= max_iter; ++it) {
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < m; i += NT) {
-                const double s = stage ? row_dot_lds<false>(mrp, mcol, mval, nullptr, sv, c0, 0.0, r0 + i)
-                                       : row_dot(mrp, mcol, mval, v, r0 + i);
+                const double s = stage ? row_dot_lds<false>(mrp, Cols<false>{mcol, nullptr}, mval, nullptr, sv, c0, 0.0, r0 + i)
+                                       : row_dot(mrp, Cols<false>{mcol, nullptr}, mval, v, r0 + i, c0);
                 w[r0 + i] = s;
                 if (stage) sw[i] = s;
                 acc[0] += s * s;
@@ -245,8 +267,8 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
             if (sig == 0.0) break;
             acc[0] = 0.0;
             for (int i = threadIdx.x; i < n; i += NT) {
-                const double s = stage ? row_dot_lds<false>(trp, tcol, tval, nullptr, sw, r0, 0.0, c0 + i)
-                                       : row_dot(trp, tcol, tval, w, c0 + i);
+                const double s = stage ? row_dot_lds<false>(trp, Cols<false>{tcol, nullptr}, tval, nullptr, sw, r0, 0.0, c0 + i)
+                                       : row_dot(trp, Cols<false>{tcol, nullptr}, tval, w, c0 + i, r0);
                 u[c0 + i] = s;
                 acc[0] += s * s;
             }
@@ -268,9 +290,10 @@ __device__ double power_norm_wg(int c0, int n, int r0, int m, const int* mrp, co
 
 // ---- the solve -----------------------------------------------------------------
 
-template <int NT, int LDSN, bool F32>
+template <int NT, int LDSN, bool F32, bool C16>
 __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchParams& P, int b, double* lds, double* sbuf)
 {
+    const Cols<C16> acol{B.acol, B.acol16}, tcol{B.tcol, B.tcol16}, qcol{B.qcol, B.qcol16};
     // per-instance values in scalar registers: the branches on them (closed
     // form vs inner solve, certificates) must be seen as uniform, or the
     // skipped side runs under an empty exec mask with its barrier count
@@ -351,11 +374,11 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             constexpr unsigned kinds = (1u << 0) | (1u << 1) | (1u << 4) | (1u << 7) | (1u << 8) |
                                        (1u << 9) | (1u << 13) | (1u << 15);
             for (int i = tid; i < n; i += NT) {
-                const double s = row_dot(B.trp, B.tcol, B.tval, yt, v0 + i);
+                const double s = row_dot(B.trp, tcol, B.tval, yt, v0 + i, r0);
                 aty[i] = s;
                 a[0] = rcomb(R_MAX, a[0], fabs(s));
                 if (k > 0) {
-                    const double wv = row_dot(B.trp, B.tcol, B.tval, ytil, v0 + i);
+                    const double wv = row_dot(B.trp, tcol, B.tval, ytil, v0 + i, r0);
                     const double wh = projR(wv, lv[i], uv[i]);
                     a[1] = rcomb(R_MAX, a[1], fabs(wv - wh));
                     a[2] += supp(-wh, lv[i], uv[i]);
@@ -363,7 +386,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 }
             }
             for (int j = tid; j < m; j += NT) {
-                const double s = row_dot(B.arp, B.acol, B.aval, B.xt, r0 + j);
+                const double s = row_dot(B.arp, acol, B.aval, B.xt, r0 + j, v0);
                 if constexpr (F32) axref[j] = s;
                 a[4] = rcomb(R_MAX, a[4], fabs(s - clampd(s, lc[j], uc[j])));
                 const double yj = yt[r0 + j];
@@ -371,14 +394,14 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 const double dv = yj - ya[j];
                 a[6] += dv * dv;
                 if (k > 0 && unb) {
-                    const double ad = row_dot(B.arp, B.acol, B.aval, B.d, r0 + j);
+                    const double ad = row_dot(B.arp, acol, B.aval, B.d, r0 + j, v0);
                     a[7] = rcomb(R_MAX, a[7], fabs(ad - projRec(ad, lc[j], uc[j])));
                 }
             }
             __syncthreads();
             for (int i = tid; i < n; i += NT) {
                 const double xi = xt[i], l = lv[i], u = uv[i];
-                const double qx = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i) : qd[i] * xi;
+                const double qx = qgen ? row_dot(B.qrp, qcol, B.qval, B.xt, v0 + i, v0) : qd[i] * xi;
                 const double r = qx + c[i] + aty[i];
                 const double rh = projR(r, l, u);
                 a[8] = rcomb(R_MAX, a[8], fabs(r - rh));
@@ -390,7 +413,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 const double dv = xi - xa[i];
                 a[14] += dv * dv;
                 if (k > 0 && unb) {
-                    const double qdv = qgen ? row_dot(B.qrp, B.qcol, B.qval, B.d, v0 + i) : qd[i] * d[i];
+                    const double qdv = qgen ? row_dot(B.qrp, qcol, B.qval, B.d, v0 + i, v0) : qd[i] * d[i];
                     a[15] = rcomb(R_MAX, a[15], fabs(qdv));
                 }
             }
@@ -476,8 +499,8 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             // ---- primal step: closed form (Section 2.2) and x_bar -----------------
             for (int i = tid; i < n; i += NT) {
                 const double s =
-                    stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
-                          : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
+                    stage ? row_dot_lds<F32>(B.trp, tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
+                          : row_dot_bulk<F32>(B.trp, tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i, r0);
                 const double xi = x[i];
                 const double v = clampd((xi * it - c[i] - s) / (qd[i] + it), lv[i], uv[i]);
                 xt[i] = v;
@@ -495,13 +518,13 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
             double st[3] = {0.0, 0.0, 0.0};   // ||g^P||^2, ||beta||^2, phit'phi
             for (int i = tid; i < n; i += NT) {
                 const double aty_i =
-                    stage ? row_dot_lds<F32>(B.trp, B.tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
-                          : row_dot_bulk<F32>(B.trp, B.tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i);
+                    stage ? row_dot_lds<F32>(B.trp, tcol, B.tval, B.tval32, sy, r0, aty[i], v0 + i)
+                          : row_dot_bulk<F32>(B.trp, tcol, B.tval, B.tval32, B.y, yref, aty[i], v0 + i, r0);
                 const double r = x[i] * it - c[i] - aty_i;
                 rhs[i] = r;
                 const double xi = xt[i];
-                const double qx = stage ? row_dot_lds<false>(B.qrp, B.qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
-                                        : row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i);
+                const double qx = stage ? row_dot_lds<false>(B.qrp, qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
+                                        : row_dot(B.qrp, qcol, B.qval, B.xt, v0 + i, v0);
                 const double gi = qx + it * xi - r;
                 g[i] = gi;
                 const Split sp = split(xi, gi, lv[i], uv[i], abar);
@@ -529,8 +552,8 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                 for (int i = tid; i < n; i += NT) {
                     const double pi = p[i], xi = xt[i];
                     const double h =
-                        (stage ? row_dot_lds<F32>(B.qrp, B.qcol, B.qval, B.qval32, sp_, v0, 0.0, v0 + i)
-                               : hp_dot<F32>(B.qrp, B.qcol, B.qval, B.qval32, B.p, v0 + i)) + it * pi;
+                        (stage ? row_dot_lds<F32>(B.qrp, qcol, B.qval, B.qval32, sp_, v0, 0.0, v0 + i)
+                               : hp_dot<F32>(B.qrp, qcol, B.qval, B.qval32, B.p, v0 + i, v0)) + it * pi;
                     hp[i] = h;
                     hs[0] += pi * h;
                     hs[1] += g[i] * pi;
@@ -572,8 +595,8 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
                     us[0] = us[1] = us[2] = 0.0;
                     for (int i = tid; i < n; i += NT) {
                         const double xi = xt[i];
-                        const double qx = stage ? row_dot_lds<false>(B.qrp, B.qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
-                                                : row_dot(B.qrp, B.qcol, B.qval, B.xt, v0 + i);
+                        const double qx = stage ? row_dot_lds<false>(B.qrp, qcol, B.qval, nullptr, sxt, v0, 0.0, v0 + i)
+                                                : row_dot(B.qrp, qcol, B.qval, B.xt, v0 + i, v0);
                         const double gi = qx + it * xi - rhs[i];
                         g[i] = gi;
                         const Split sp = split(xi, gi, lv[i], uv[i], abar);
@@ -607,8 +630,8 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
         constexpr unsigned kinds7 = (1u << 2) | (1u << 5);   // max slots, the rest sums
         for (int j = tid; j < m; j += NT) {
             const double s =
-                stage ? row_dot_lds<F32>(B.arp, B.acol, B.aval, B.aval32, sx, v0, axref[j], r0 + j)
-                      : row_dot_bulk<F32>(B.arp, B.acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j);
+                stage ? row_dot_lds<F32>(B.arp, acol, B.aval, B.aval32, sx, v0, axref[j], r0 + j)
+                      : row_dot_bulk<F32>(B.arp, acol, B.aval, B.aval32, xbar, xref, axref[j], r0 + j, v0);
             const double yj = y[j], l = lc[j], u = uc[j];
             const double v = yj / sigma + s;
             const double ytj = sigma * (v - clampd(v, l, u));
@@ -672,7 +695,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
 
 // WPE: waves per SIMD the register allocation must allow (1: no limit
 // beyond the workgroup size; more trades spills for resident instances)
-template <int NT, int LDSN, int WPE, bool F32>
+template <int NT, int LDSN, int WPE, bool F32, bool C16>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_batch_solve(BatchDev B, BatchParams P)
 {
     __shared__ double lds[16 * (NT / 64)];
@@ -685,7 +708,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         __syncthreads();
         if (b >= B.count) return;
         if (B.order != nullptr) b = uniform_int(B.order[b]);
-        batch_solve_one<NT, LDSN, F32>(B, P, b, lds, sbuf);
+        batch_solve_one<NT, LDSN, F32, C16>(B, P, b, lds, sbuf);
     }
 }
 
@@ -698,7 +721,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 template <int NT, int LDSN, int WPE, bool F32>
 hipError_t solve_shape(const BatchDev& B, const BatchParams& P, int grid, hipStream_t s)
 {
-    k_batch_solve<NT, LDSN, WPE, F32><<<grid, NT, 0, s>>>(B, P);
+    if (B.acol16) k_batch_solve<NT, LDSN, WPE, F32, true><<<grid, NT, 0, s>>>(B, P);
+    else k_batch_solve<NT, LDSN, WPE, F32, false><<<grid, NT, 0, s>>>(B, P);
     return hipGetLastError();
 }
 
@@ -718,8 +742,8 @@ int resident_per_cu(int which)
 {
     int nb = 0;
     hipError_t e;
-    if (which == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, false>, NT, 0);
-    else if (which == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, true>, NT, 0);
+    if (which == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, false, true>, NT, 0);
+    else if (which == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_solve<NT, LDSN, WPE, true, true>, NT, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_norm<NT, LDSN>, NT, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }

@@ -1444,6 +1444,28 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
         (rc = bupload(bt, &B.lv, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv, uvv.data(), (size_t)n)) ||
         (rc = bupload(bt, &B.lc, lcv.data(), (size_t)m)) || (rc = bupload(bt, &B.uc, ucv.data(), (size_t)m)))
         return bail(rc);
+    {
+        // 16-bit column indices local to the instance when every instance
+        // is small enough (the blocks were checked to be diagonal above)
+        bool small = true;
+        for (int64_t i = 0; i < count && small; ++i)
+            small = var_off[i + 1] - var_off[i] <= 65536 && row_off[i + 1] - row_off[i] <= 65536;
+        if (small) {
+            std::vector<unsigned short> a16((size_t)nnz), t16(tj.size()), q16((size_t)qnnz);
+            for (int64_t i = 0; i < count; ++i) {
+                for (int64_t r = row_off[i]; r < row_off[i + 1]; ++r)
+                    for (int64_t q = Ap[r]; q < Ap[r + 1]; ++q) a16[q] = (unsigned short)(Aj[q] - var_off[i]);
+                for (int64_t v = var_off[i]; v < var_off[i + 1]; ++v) {
+                    for (int64_t q = tp[v]; q < tp[v + 1]; ++q) t16[q] = (unsigned short)(tj[q] - row_off[i]);
+                    for (int64_t q = Qp[v]; q < Qp[v + 1]; ++q) q16[q] = (unsigned short)(Qj[q] - var_off[i]);
+                }
+            }
+            if ((rc = bupload(bt, &B.acol16, a16.data(), a16.size())) ||
+                (rc = bupload(bt, &B.tcol16, t16.data(), t16.size())) ||
+                (rc = bupload(bt, &B.qcol16, q16.data(), q16.size())))
+                return bail(rc);
+        }
+    }
     double** nv[] = {&B.x, &B.xa, &B.xt, &B.xbar, &B.aty, &B.d, &B.rhs, &B.g, &B.p, &B.hp, &B.xref};
     for (double** p : nv)
         if ((rc = balloc(bt, p, (size_t)n))) return bail(rc);

@@ -264,6 +264,9 @@ struct BatchDev {
     const double* tval = nullptr;
     const int *qrp = nullptr, *qcol = nullptr;  // Q (block-diagonal, global indices)
     const double* qval = nullptr;
+    // the columns of A, A' and Q as 16-bit indices local to the instance
+    // (all three set when every instance has n_b, m_b < 65536, else NULL)
+    const unsigned short *acol16 = nullptr, *tcol16 = nullptr, *qcol16 = nullptr;
     // FP32 copies of the values for the bulk products of a mixed-precision
     // solve (all NULL in FP64)
     const float *aval32 = nullptr, *tval32 = nullptr, *qval32 = nullptr;
