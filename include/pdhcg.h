@@ -338,7 +338,7 @@ typedef struct {
                                  limit; 3000 */
     int32_t batch_lanes;      /* batched launches in flight for diagonal-Q requests; 2 */
     int32_t general_lanes;    /* batched launches in flight for non-diagonal-Q requests; 2 */
-    int32_t single_workers;   /* single-path solves in flight; 8 */
+    int32_t single_workers;   /* single-path solves in flight; 4 */
     int32_t max_batch;        /* instances per batched launch; 1024 */
     int32_t batch_shape;      /* launch shape of the batched launches of diagonal-Q requests
                                  (qp_batch_set_schedule), -1: the library default */

@@ -333,7 +333,7 @@ qp_server_config qp_server_config_default(void)
     c.general_max_dim = 3000;
     c.batch_lanes = 2;
     c.general_lanes = 2;
-    c.single_workers = 8;
+    c.single_workers = 4;
     c.max_batch = 1024;
     c.batch_shape = -1;
     c.batch_order = -1;
