@@ -92,7 +92,7 @@ def cpu_baseline(q, gpu_units_per_solve, sample_iters):
     }
 
 
-def batch_bytes(q, iters, vb=12):
+def batch_bytes(q, iters, vb=12, bb=16):
     """Algorithmic bytes of one instance's iterations in the batched kernel:
     the A and A' products (vb B per nonzero each: the value, 8 in FP64 or 4
     in FP32, and the column index, 2 when every instance is below 65536
@@ -100,8 +100,9 @@ def batch_bytes(q, iters, vb=12):
     the primal step (x, c, q, l_v, u_v read; x_T, x_bar written), the dual
     step (x_bar gathered once; y, y anchor, l_c, u_c read; y_T, y written)
     and the Halpern step on x (x_T, x, anchor read; x written) -- counted
-    as HBM traffic, as in the form that keeps no iterate on chip."""
-    per_iter = 2 * vb * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * (7 + 1 + 4) + 8 * q.m * 6
+    as HBM traffic, as in the form that keeps no iterate on chip; the box
+    costs bb bytes per variable (bound_bytes of the whole batch)."""
+    per_iter = 2 * vb * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * 10 + bb * q.n + 8 * q.m * 6
     return per_iter * iters
 
 
@@ -151,7 +152,11 @@ def main_batch(args, torch, P, I):
     infos = [bs.result(i).info for i in range(len(qs))]
     iters = [i["iterations"] for i in infos]
     col_b = 2 if max(max(q.n, q.m) for q in qs) <= 65536 else 4
-    nbytes = sum(batch_bytes(q, it, (4 if mixed else 8) + col_b) for q, it in zip(qs, iters))
+    whole = type("Box", (), {"n": sum(q.n for q in qs),
+                             "lb": np.concatenate([np.full(q.n, -np.inf) if q.lb is None else q.lb for q in qs]),
+                             "ub": np.concatenate([np.full(q.n, np.inf) if q.ub is None else q.ub for q in qs])})
+    bb = bound_bytes(whole)
+    nbytes = sum(batch_bytes(q, it, (4 if mixed else 8) + col_b, bb) for q, it in zip(qs, iters))
     kernel_s = float(np.median(lat))
     bs.close()
     # the same instances one at a time through the single-QP path, FP64

@@ -87,6 +87,13 @@ __device__ void wg_reduce_min3(double (&v)[3], double* lds)
     __syncthreads();
 }
 
+// one instance's side of the box: entry i of the instance starting at off
+struct BoundAt {
+    BoundVec b;
+    int off;
+    __device__ __forceinline__ double operator[](int i) const { return b[(long long)off + i]; }
+};
+
 // Column indices of a packed matrix: global 32-bit ones, or 16-bit indices
 // local to the instance (column = off + local), which cut the index bytes
 // of every product in half when every instance has fewer than 65536
@@ -304,7 +311,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
     double* x = B.x + v0;   double* xa = B.xa + v0; double* xt = B.xt + v0;
     double* xbar = B.xbar;  double* aty = B.aty + v0; double* d = B.d + v0;
     const double* c = B.c + v0; const double* qd = B.qd + v0;
-    const double* lv = B.lv + v0; const double* uv = B.uv + v0;
+    const BoundAt lv{B.lv, v0}, uv{B.uv, v0};
     double* y = B.y + r0;   double* ya = B.ya + r0;  double* yt = B.yt;
     double* ytil = B.ytil;
     const double* lc = B.lc + r0; const double* uc = B.uc + r0;

@@ -346,25 +346,24 @@ int upload(qp_handle* h, T** p, const T* src, size_t count)
     return 0;
 }
 
-// The variable bounds as two BoundVec (pdhcg_internal.h): one pair shared
-// by every variable, a byte class per variable when at most 256 distinct
-// (l, u) pairs occur (compared bit for bit, so every value is kept
-// exactly), else the two arrays.  PDHCG_BOUND_STORAGE=arrays in the
-// environment forces the arrays (to check that every storage gives the
-// same bits).
-int upload_bounds(qp_handle* h, DevState& S, const std::vector<double>& lv, const std::vector<double>& uv)
+// Storage of the variable bounds (BoundVec, pdhcg_internal.h): 1 when every
+// variable has the same (l, u) pair, 2 when at most 256 distinct pairs occur
+// (compared bit for bit, so every value is kept exactly; cls, tl, tu are
+// filled), else 0 (the two arrays).  PDHCG_BOUND_STORAGE=arrays in the
+// environment forces 0 (to check that every storage gives the same bits).
+int classify_bounds(const std::vector<double>& lv, const std::vector<double>& uv, std::vector<unsigned char>& cls,
+                    std::vector<double>& tl, std::vector<double>& tu)
 {
     const size_t n = lv.size();
     const char* force = std::getenv("PDHCG_BOUND_STORAGE");
-    const bool arrays_only = force && std::strcmp(force, "arrays") == 0;
+    if (n == 0 || (force && std::strcmp(force, "arrays") == 0)) return 0;
     typedef std::pair<uint64_t, uint64_t> Key;
     std::map<Key, int> index;
     std::vector<Key> keys;
-    std::vector<unsigned char> cls(n);
-    bool few = !arrays_only;
+    cls.assign(n, 0);
     int last = -1;
     Key lastkey{0, 0};
-    for (size_t i = 0; i < n && few; ++i) {
+    for (size_t i = 0; i < n; ++i) {
         Key key;
         std::memcpy(&key.first, &lv[i], sizeof(double));
         std::memcpy(&key.second, &uv[i], sizeof(double));
@@ -373,7 +372,7 @@ int upload_bounds(qp_handle* h, DevState& S, const std::vector<double>& lv, cons
             if (it != index.end()) {
                 last = it->second;
             } else {
-                if (keys.size() == 256) { few = false; break; }
+                if (keys.size() == 256) return 0;
                 last = (int)keys.size();
                 index.emplace(key, last);
                 keys.push_back(key);
@@ -382,36 +381,42 @@ int upload_bounds(qp_handle* h, DevState& S, const std::vector<double>& lv, cons
         }
         cls[i] = (unsigned char)last;
     }
+    tl.resize(keys.size());
+    tu.resize(keys.size());
+    for (size_t c = 0; c < keys.size(); ++c) {
+        std::memcpy(&tl[c], &keys[c].first, sizeof(double));
+        std::memcpy(&tu[c], &keys[c].second, sizeof(double));
+    }
+    return keys.size() == 1 ? 1 : 2;
+}
+
+int upload_bounds(qp_handle* h, DevState& S, const std::vector<double>& lv, const std::vector<double>& uv)
+{
+    std::vector<unsigned char> cls;
+    std::vector<double> tl, tu;
+    const int mode = classify_bounds(lv, uv, cls, tl, tu);
     S.lv = BoundVec{};
     S.uv = BoundVec{};
+    S.lv.mode = S.uv.mode = mode;
     int rc;
-    if (few && keys.size() == 1) {
-        S.lv.mode = S.uv.mode = 1;
-        S.lv.k = lv[0];
-        S.uv.k = uv[0];
-        return 0;
-    }
-    if (few) {
-        std::vector<double> tl(keys.size()), tu(keys.size());
-        for (size_t c = 0; c < keys.size(); ++c) {
-            std::memcpy(&tl[c], &keys[c].first, sizeof(double));
-            std::memcpy(&tu[c], &keys[c].second, sizeof(double));
-        }
+    if (mode == 1) {
+        S.lv.k = tl[0];
+        S.uv.k = tu[0];
+    } else if (mode == 2) {
         unsigned char* dc = nullptr;
         double *dl = nullptr, *du = nullptr;
-        if ((rc = upload(h, &dc, cls.data(), n)) || (rc = upload(h, &dl, tl.data(), tl.size())) ||
+        if ((rc = upload(h, &dc, cls.data(), cls.size())) || (rc = upload(h, &dl, tl.data(), tl.size())) ||
             (rc = upload(h, &du, tu.data(), tu.size())))
             return rc;
-        S.lv.mode = S.uv.mode = 2;
         S.lv.cls = S.uv.cls = dc;
         S.lv.tab = dl;
         S.uv.tab = du;
-        return 0;
+    } else {
+        double *dl = nullptr, *du = nullptr;
+        if ((rc = upload(h, &dl, lv.data(), lv.size())) || (rc = upload(h, &du, uv.data(), uv.size()))) return rc;
+        S.lv.a = dl;
+        S.uv.a = du;
     }
-    double *dl = nullptr, *du = nullptr;
-    if ((rc = upload(h, &dl, lv.data(), n)) || (rc = upload(h, &du, uv.data(), n))) return rc;
-    S.lv.a = dl;
-    S.uv.a = du;
     return 0;
 }
 
@@ -1441,9 +1446,27 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
         (rc = bupload(bt, &B.aval, Av, (size_t)nnz)) || (rc = bupload(bt, &B.trp, trp32.data(), trp32.size())) ||
         (rc = bupload(bt, &B.tcol, tj.data(), tj.size())) || (rc = bupload(bt, &B.tval, tv.data(), tv.size())) ||
         (rc = bupload(bt, &B.qd, qd.data(), (size_t)n)) || (rc = bupload(bt, &B.c, c, (size_t)n)) ||
-        (rc = bupload(bt, &B.lv, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv, uvv.data(), (size_t)n)) ||
         (rc = bupload(bt, &B.lc, lcv.data(), (size_t)m)) || (rc = bupload(bt, &B.uc, ucv.data(), (size_t)m)))
         return bail(rc);
+    {
+        // the box as one pair, byte classes or arrays (as for one problem)
+        std::vector<unsigned char> cls;
+        std::vector<double> tl, tu;
+        const int mode = classify_bounds(lvv, uvv, cls, tl, tu);
+        B.lv.mode = B.uv.mode = mode;
+        if (mode == 1) {
+            B.lv.k = tl[0];
+            B.uv.k = tu[0];
+        } else if (mode == 2) {
+            if ((rc = bupload(bt, &B.lv.cls, cls.data(), cls.size())) ||
+                (rc = bupload(bt, &B.lv.tab, tl.data(), tl.size())) || (rc = bupload(bt, &B.uv.tab, tu.data(), tu.size())))
+                return bail(rc);
+            B.uv.cls = B.lv.cls;
+        } else {
+            if ((rc = bupload(bt, &B.lv.a, lvv.data(), (size_t)n)) || (rc = bupload(bt, &B.uv.a, uvv.data(), (size_t)n)))
+                return bail(rc);
+        }
+    }
     {
         // 16-bit column indices local to the instance when every instance
         // is small enough (the blocks were checked to be diagonal above)

@@ -270,7 +270,8 @@ struct BatchDev {
     // FP32 copies of the values for the bulk products of a mixed-precision
     // solve (all NULL in FP64)
     const float *aval32 = nullptr, *tval32 = nullptr, *qval32 = nullptr;
-    const double *qd = nullptr, *c = nullptr, *lv = nullptr, *uv = nullptr, *lc = nullptr, *uc = nullptr;
+    const double *qd = nullptr, *c = nullptr, *lc = nullptr, *uc = nullptr;
+    BoundVec lv, uv;                            // variable bounds (n), as for one problem
     // per instance
     const double *eta = nullptr, *omega0 = nullptr, *cmax = nullptr, *bscale = nullptr, *gammaq = nullptr;
     const double* normq = nullptr;              // ||Q_b||_2 (x 1.01 for a non-diagonal Q_b)

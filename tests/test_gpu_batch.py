@@ -196,3 +196,22 @@ def test_batch_tune_picks_fastest_and_caches(torch, tmp_path):
         e2 = bs2.tune(cache=cache)
         assert e2["cached"] and (e2["shape"], e2["order"]) == (e["shape"], e["order"])
         assert bs2.schedule() == (e["shape"], e["order"])
+
+
+def test_batch_bound_storage_gives_the_same_bits(torch, monkeypatch):
+    """The batch's box as byte classes (MPC: two (l, u) pairs) or as arrays:
+    the same bits."""
+    qs = [I.mpc(i) for i in range(50, 56)] + [I.mpc(103, infeasible=True), I.tiny_lp(7)]
+    params = P.qp_params_default(precision=P.PRECISION_MIXED)
+
+    def run():
+        with P.BatchSolver(qs) as bs:
+            bs.solve(params)
+            return [bs.result(i) for i in range(len(qs))]
+
+    a = run()
+    monkeypatch.setenv("PDHCG_BOUND_STORAGE", "arrays")
+    b = run()
+    for q, g, h in zip(qs, a, b):
+        assert g.status == h.status and g.info["iterations"] == h.info["iterations"], q.name
+        assert np.array_equal(g.x, h.x) and np.array_equal(g.y, h.y), q.name
