@@ -399,7 +399,7 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="arrivals per second of the served stream")
     ap.add_argument("--lanes", type=int, default=2, help="server lanes for diagonal-Q requests")
     ap.add_argument("--general-lanes", type=int, default=2, help="server lanes for non-diagonal-Q requests")
-    ap.add_argument("--workers", type=int, default=4, help="server single-path workers")
+    ap.add_argument("--workers", type=int, default=5, help="server single-path workers")
     ap.add_argument("--batch-max-dim", type=int, default=20000)
     ap.add_argument("--general-max-dim", type=int, default=3000)
     ap.add_argument("--linger-us", type=float, default=200.0)

@@ -338,14 +338,17 @@ typedef struct {
                                  limit; 3000 */
     int32_t batch_lanes;      /* batched launches in flight for diagonal-Q requests; 2 */
     int32_t general_lanes;    /* batched launches in flight for non-diagonal-Q requests; 2 */
-    int32_t single_workers;   /* single-path solves in flight; 4 */
+    int32_t single_workers;   /* single-path solves in flight; 5 */
     int32_t max_batch;        /* instances per batched launch; 1024 */
     int32_t batch_shape;      /* launch shape of the batched launches of diagonal-Q requests
                                  (qp_batch_set_schedule), -1: the library default */
     int32_t batch_order;      /* their queue order (0 or 1), -1: the library default */
     int32_t general_shape;    /* launch shape of the batched launches of non-diagonal-Q
                                  requests, -1: qp_batch_default_shape(1) */
-    int32_t pad;
+    int32_t diag_workers;     /* of the single-path workers, those that take only
+                                 diagonal-Q requests (or any request when no other
+                                 worker exists), <= single_workers; -1: 1 when
+                                 single_workers >= 2, else 0 */
     double batch_linger_us;   /* a free lane waits up to this long (from the oldest waiting
                                  request's arrival) for more requests before launching; 200 */
 } qp_server_config;

@@ -73,7 +73,7 @@ class ServerConfig(C.Structure):
                 ("batch_lanes", C.c_int32), ("general_lanes", C.c_int32),
                 ("single_workers", C.c_int32), ("max_batch", C.c_int32),
                 ("batch_shape", C.c_int32), ("batch_order", C.c_int32),
-                ("general_shape", C.c_int32), ("pad", C.c_int32),
+                ("general_shape", C.c_int32), ("diag_workers", C.c_int32),
                 ("batch_linger_us", C.c_double)]
 
 

@@ -10,7 +10,10 @@
 // iteration) and instances with an inner solve (non-diagonal Q), each with
 // its own queue, so fast requests never wait behind slow ones.  Requests too
 // large for one workgroup go to worker threads that solve them one at a time
-// on the single-problem path (each handle has its own stream).  Admission is by
+// on the single-problem path (each handle has its own stream); these workers
+// come in the same two classes, and the diagonal-Q workers never take an
+// inner-solve request, so a fast single-path request (a large portfolio)
+// does not queue behind slow ones either.  Admission is by
 // device bytes: a request starts only when the bytes of everything in flight
 // plus its own stay within the budget; the waiting queue is first come,
 // first served within each route.
@@ -89,7 +92,8 @@ struct qp_server {
     double t0 = 0.0;
     std::mutex mu;
     std::condition_variable cv_sched, cv_work, cv_done;
-    std::deque<Request*> bq[2], sq;   // waiting: per batched class, single path
+    std::deque<Request*> bq[2], sq[2];   // waiting: per class, batched and single path
+    int workers_of[2] = {0, 0};          // single-path workers per class
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     int64_t next_id = 0;
     size_t in_flight = 0;
@@ -280,18 +284,30 @@ void scheduler(qp_server* s)
     }
 }
 
-void worker(qp_server* s)
+// the single-path queue a worker of class k takes its next request from
+// (own class first; a general worker helps with diagonal-Q requests, and a
+// diagonal-Q worker takes general ones only when there is no general
+// worker), or -1 when nothing it may take fits the budget
+int pick_queue(const qp_server* s, int k)
+{
+    auto fits = [&](int q) {
+        return !s->sq[q].empty() && s->in_flight + s->sq[q].front()->bytes <= (size_t)s->cfg.device_budget;
+    };
+    if (fits(k)) return k;
+    if ((k == 1 || s->workers_of[1] == 0) && fits(1 - k)) return 1 - k;
+    return -1;
+}
+
+void worker(qp_server* s, int k)
 {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_work.wait(lk, [&] {
-            return s->stop ||
-                   (!s->sq.empty() && s->in_flight + s->sq.front()->bytes <= (size_t)s->cfg.device_budget);
-        });
+        int q = -1;
+        s->cv_work.wait(lk, [&] { return s->stop || (q = pick_queue(s, k)) >= 0; });
         if (s->stop) break;
-        Request* r = s->sq.front();
-        s->sq.pop_front();
+        Request* r = s->sq[q].front();
+        s->sq[q].pop_front();
         s->in_flight += r->bytes;
         r->state = 1;
         r->times.started = rel(s);
@@ -333,12 +349,12 @@ qp_server_config qp_server_config_default(void)
     c.general_max_dim = 3000;
     c.batch_lanes = 2;
     c.general_lanes = 2;
-    c.single_workers = 4;
+    c.single_workers = 5;
     c.max_batch = 1024;
     c.batch_shape = -1;
     c.batch_order = -1;
     c.general_shape = -1;
-    c.pad = 0;
+    c.diag_workers = -1;
     c.batch_linger_us = 200.0;
     return c;
 }
@@ -353,7 +369,8 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
         c.general_lanes < 0 || c.single_workers < 0 || c.batch_lanes + c.general_lanes + c.single_workers < 1 ||
         c.max_batch < 1 || !(c.batch_linger_us >= 0.0) || c.batch_shape < -1 ||
         c.batch_shape >= qp_batch_num_shapes() || c.batch_order < -1 || c.batch_order > 1 ||
-        c.general_shape < -1 || c.general_shape >= qp_batch_num_shapes())
+        c.general_shape < -1 || c.general_shape >= qp_batch_num_shapes() || c.diag_workers < -1 ||
+        c.diag_workers > c.single_workers)
         return fail(QP_ERR_INVALID_ARG, "invalid server configuration");
     if (!(p.tol > 0.0) || p.max_iter < 0 || p.check_every < 1 ||
         (p.precision != QP_PRECISION_FP64 && p.precision != QP_PRECISION_MIXED))
@@ -380,7 +397,9 @@ int qp_server_create(const qp_server_config* cfg, const qp_params* params, qp_se
         }
     }
     if (c.batch_lanes + c.general_lanes > 0) s->sched = std::thread(scheduler, s);
-    for (int i = 0; i < c.single_workers; ++i) s->workers.emplace_back(worker, s);
+    s->workers_of[0] = c.diag_workers >= 0 ? c.diag_workers : (c.single_workers >= 2 ? 1 : 0);
+    s->workers_of[1] = c.single_workers - s->workers_of[0];
+    for (int i = 0; i < c.single_workers; ++i) s->workers.emplace_back(worker, s, i < s->workers_of[0] ? 0 : 1);
     *out = s;
     return 0;
 }
@@ -476,8 +495,8 @@ int64_t qp_server_submit(qp_server* s, int64_t n, int64_t m,
         s->bq[raw->klass].push_back(raw);
         s->cv_sched.notify_one();
     } else {
-        s->sq.push_back(raw);
-        s->cv_work.notify_one();
+        s->sq[raw->klass].push_back(raw);
+        s->cv_work.notify_all();
     }
     g_err.clear();
     return raw->id;
@@ -524,7 +543,8 @@ void qp_server_destroy(qp_server* s)
         s->stop = true;
         s->bq[0].clear();
         s->bq[1].clear();
-        s->sq.clear();
+        s->sq[0].clear();
+        s->sq[1].clear();
     }
     s->cv_sched.notify_all();
     s->cv_work.notify_all();

@@ -265,11 +265,12 @@ def test_batch_shape_table_and_schedule_validation():
     for kw in ({"batch_shape": ns}, {"batch_shape": -2}, {"batch_order": 2}):
         bad = P.qp_server_config_default(**kw)
         assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
-    for kw in ({"general_shape": ns}, {"general_shape": -2}):
+    for kw in ({"general_shape": ns}, {"general_shape": -2}, {"diag_workers": -2},
+               {"diag_workers": 5, "single_workers": 4}):
         bad = P.qp_server_config_default(**kw)
         assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
     c = P.qp_server_config_default()
-    assert c.batch_shape == -1 and c.batch_order == -1 and c.general_shape == -1
+    assert c.batch_shape == -1 and c.batch_order == -1 and c.general_shape == -1 and c.diag_workers == -1
     assert P.qp_batch_default_shape(False) == 1
     g = P.qp_batch_default_shape(True)
     assert 0 <= g < ns and P.qp_batch_shape_info(g)[0] >= 512
