@@ -162,3 +162,24 @@ def test_serve_with_a_chosen_batch_schedule(torch):
             a = bs.result(0)
         assert g.status == a.status == P.OPTIMAL, q.name
         assert np.array_equal(g.x, a.x) and np.array_equal(g.y, a.y), q.name
+
+
+def test_serve_single_path_worker_classes(torch):
+    """No batched lanes: every request runs on the single-problem path, the
+    diagonal-Q ones on the reserved worker, the others on the general one
+    (or on the reserved one only when no general worker exists)."""
+    qs = [I.portfolio(5, n_assets=10000, k_factors=50), I.random_small(11), I.tiny_lp(8),
+          I.random_small(12, n=300), I.mpc(700)]
+    params = P.qp_params_default()
+    for cfg in ({"single_workers": 2, "diag_workers": 1}, {"single_workers": 1, "diag_workers": 1}):
+        with P.Server(params, batch_lanes=0, general_lanes=0, **cfg) as srv:
+            ids = [srv.submit(q) for q in qs]
+            out = []
+            for rid in ids:
+                assert srv.wait(rid, 120.0) > 0, cfg
+                out.append(srv.result(rid))
+        for q, (g, t) in zip(qs, out):
+            assert t["route"] == 1, (cfg, q.name)
+            a = _alone(q, params, 1)
+            assert g.status == a.status, (cfg, q.name)
+            assert np.array_equal(g.x, a.x) and np.array_equal(g.y, a.y), (cfg, q.name)
