@@ -516,6 +516,18 @@ def main():
             kern[name] = {"avg_us": round(1e3 * sum(i["fam_ms"][j] for i in infos) / tj, 3),
                           "launches_per_solve": infos[-1]["fam_launches"][j]}
     units = infos[-1]["iterations"] + infos[-1]["inner_iterations"]
+    # the product's random gathers (one per nonzero) against the device's
+    # measured gather rate for the same vector length and part keying: the
+    # bound this product actually meets (outside the timed region)
+    gather = None
+    if timed:
+        peak_g = P.measure_gather_rate(q.n, q.nnz_Q, 20)
+        ach_g = q.nnz_Q * active / (avg_us * 1e-6 * launches)
+        gather = {"achieved": ach_g / 1e9, "peak": peak_g / 1e9, "unit": "G gathers/s",
+                  "frac": ach_g / peak_g if peak_g > 0 else None,
+                  "peak_source": "qp_measure_gather_rate (random 8-byte gathers, XCD-keyed parts, "
+                                 f"n={q.n}, {q.nnz_Q} per launch)"}
+        log(f"gather rate: product {ach_g / 1e9:.0f} G/s, device {peak_g / 1e9:.0f} G/s")
 
     out = {
         "metric": METRIC,
@@ -543,6 +555,7 @@ def main():
                      "kernel": "inner H p product (k_spmv<EpiStepA> + k_rows<EpiStepA>)",
                      "bytes_per_launch": nbytes, "avg_us": avg_us, "timed_launches": timed,
                      "launches": launches, "active_launches": active},
+        "gather_roofline": gather,
         "kernels": kern,
         "setup_s": info["setup_seconds"],
     }

@@ -391,6 +391,19 @@ int qp_server_result(qp_server* s, int64_t id, double* x, double* y, qp_info* in
 /* Finish the requests in flight, drop the waiting ones and stop. */
 void qp_server_destroy(qp_server* s);
 
+/* ---- measurement utility (not part of the method) --------------------- */
+
+/* The device's rate of random 8-byte gathers from a vector of n doubles
+ * (n >= 4, < 2^31), with gathering blocks keyed to the same four XCD column
+ * parts as the column-partitioned products: `gathers` (>= 2048) pseudo-
+ * random reads per launch, timed over `repeats` launches after 3 untimed
+ * ones on the null stream.  Allocates and frees its own device memory.
+ * *gathers_per_s (host) receives the rate.  Returns 0, or
+ * QP_ERR_INVALID_ARG / QP_ERR_DEVICE.  The large products are bound by this
+ * rate rather than by HBM bytes; the bench reports the product's own gather
+ * rate against it. */
+int qp_measure_gather_rate(int64_t n, int64_t gathers, int32_t repeats, double* gathers_per_s);
+
 /* ---- host-only diagnostics (no device call) --------------------------- */
 
 /* The SpMV work schedule the library builds for a CSR with `rows` rows and

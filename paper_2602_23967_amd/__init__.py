@@ -131,6 +131,7 @@ def lib():
         L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
+        L.qp_measure_gather_rate.argtypes = [_i64, _i64, C.c_int32, _dp]
         L.qp_batch_num_shapes.argtypes = []
         L.qp_batch_default_shape.argtypes = [C.c_int32]
         L.qp_batch_shape_info.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -397,6 +398,14 @@ def qp_batch_destroy(h):
 
 def qp_batch_num_shapes() -> int:
     return _check(lib().qp_batch_num_shapes())
+
+
+def measure_gather_rate(n: int, gathers: int, repeats: int = 20) -> float:
+    """Random 8-byte gathers per second from n doubles, XCD-keyed parts
+    (qp_measure_gather_rate: a measurement utility, not part of the method)."""
+    out = C.c_double(0.0)
+    _check(lib().qp_measure_gather_rate(n, gathers, repeats, C.byref(out)))
+    return out.value
 
 
 def qp_batch_default_shape(general: bool = False) -> int:

@@ -9,7 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdhcg_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "host.cpp", "serve.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "calib.hip", "host.cpp", "serve.cpp")]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed FP32 instructions anywhere (hipcc's host pass warns about

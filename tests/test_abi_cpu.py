@@ -244,6 +244,15 @@ def test_batch_rejects_long_rows():
     assert "QP_BATCH_MAX_ROW" in P.qp_last_error()
 
 
+def test_gather_rate_validation():
+    import ctypes as C
+    L = P.lib()
+    out = C.c_double(0.0)
+    for n, g, r in ((2, 4096, 1), (1000, 100, 1), (1000, 4096, 0)):
+        assert L.qp_measure_gather_rate(n, g, r, C.byref(out)) == P.ERR_INVALID_ARG
+    assert L.qp_measure_gather_rate(1000, 4096, 1, None) == P.ERR_INVALID_ARG
+
+
 def test_batch_shape_table_and_schedule_validation():
     import ctypes as C
     ns = P.qp_batch_num_shapes()

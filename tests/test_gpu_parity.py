@@ -405,3 +405,13 @@ def test_bound_storage_gives_the_same_bits(torch, make, monkeypatch):
     assert g.info["inner_iterations"] == a.info["inner_iterations"]
     assert np.array_equal(g.x, a.x) and np.array_equal(g.y, a.y)
     _assert_kkt(q, g)
+
+
+def test_gather_rate_measurement(torch):
+    """The gather-rate utility runs and gives a rate between the product's
+    and a bound no device reaches (one gather per clock per CU at 3 GHz)."""
+    g = P.measure_gather_rate(1_000_000, 11_000_000, 5)
+    print(f"gather rate {g / 1e9:.0f} G/s", flush=True)
+    assert 10e9 < g < 256 * 3e9 * 4
+    with pytest.raises(P.QPError):
+        P.measure_gather_rate(2, 11_000_000, 5)
