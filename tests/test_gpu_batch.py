@@ -215,3 +215,46 @@ def test_batch_bound_storage_gives_the_same_bits(torch, monkeypatch):
     for q, g, h in zip(qs, a, b):
         assert g.status == h.status and g.info["iterations"] == h.info["iterations"], q.name
         assert np.array_equal(g.x, h.x) and np.array_equal(g.y, h.y), q.name
+
+
+def _wide_separable(n=70000, m=60, per_row=120, seed=7):
+    """A diagonal-Q QP with more than 65536 variables (short rows and
+    columns, so it fits the batched kernel): a batch holding it takes the
+    32-bit column indices."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(m):
+        cj = np.sort(rng.choice(n, size=per_row, replace=False))
+        rows += [i] * per_row
+        cols += list(cj)
+    A = sp.csr_matrix((rng.normal(size=len(rows)), (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    Q = sp.diags(rng.uniform(0.1, 1.0, size=n)).tocsr()
+    sense = np.array([ord("E")] * (m // 2) + [ord("G")] * (m - m // 2), dtype=np.uint8)
+    b = A @ x0
+    return I.QP(n=n, m=m, Q=Q, A=A, c=rng.normal(size=n), b=b, sense=sense.tobytes(),
+                lb=np.full(n, -1.0), ub=np.full(n, 1.0), name="wide_separable")
+
+
+def test_batch_wide_instance_uses_32bit_columns(torch):
+    """A batch with an instance of more than 65536 variables runs the
+    products on 32-bit column indices; results still match the oracle, and
+    a small instance in it gets the result it gets in a 16-bit batch up to
+    the last bits of its reductions."""
+    wide = _wide_separable()
+    small = I.mpc(9)
+    with P.BatchSolver([wide, small]) as bs:
+        bs.solve()
+        gw, gs = bs.result(0), bs.result(1)
+    ow = oracle.solve(wide)
+    assert gw.status == ow.status == P.OPTIMAL
+    k = oracle.kkt(wide, gw.x, gw.y)
+    assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6, k
+    assert gw.info["primal_obj"] == pytest.approx(ow.info["primal_obj"], rel=1e-6, abs=1e-6)
+    with P.BatchSolver([small]) as bs:
+        bs.solve()
+        a = bs.result(0)
+    assert gs.status == a.status == P.OPTIMAL
+    assert gs.info["iterations"] == a.info["iterations"]
+    assert np.array_equal(gs.x, a.x) and np.array_equal(gs.y, a.y)
