@@ -415,3 +415,25 @@ def test_gather_rate_measurement(torch):
     assert 10e9 < g < 256 * 3e9 * 4
     with pytest.raises(P.QPError):
         P.measure_gather_rate(2, 11_000_000, 5)
+
+
+def test_diagonal_q_with_dense_column_matches_oracle(torch):
+    """Diagonal Q and a column of A in every row (A' has a row longer than a
+    row block, completed in the closed-form step's own finishing kernel, so
+    that step's finishing work is not carried into the dual step's)."""
+    rng = np.random.default_rng(21)
+    n, m = 3000, 2600
+    A = sp.random(m, n, density=3.0 / n, random_state=rng, data_rvs=rng.standard_normal).tolil()
+    A[:, 0] = 0.05 * rng.normal(size=(m, 1))
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    x0 = rng.uniform(-0.5, 0.5, size=n)
+    q = I.QP(n=n, m=m, Q=sp.diags(rng.uniform(0.5, 2.0, size=n)).tocsr(), A=A, c=rng.normal(size=n),
+             b=A @ x0 - 0.05, sense=bytes([ord("G")] * m),
+             lb=np.full(n, -1.0), ub=np.full(n, 1.0), name="dense_column")
+    assert np.diff(sp.csc_matrix(A).indptr).max() > 2048
+    g = _gpu_solve(q)
+    o = oracle.solve(q)
+    assert g.status == o.status == P.OPTIMAL
+    _assert_kkt(q, g)
+    assert g.info["primal_obj"] == pytest.approx(o.info["primal_obj"], rel=1e-6, abs=1e-6)
