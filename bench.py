@@ -395,7 +395,7 @@ def main():
                     help="outer iteration cap (lower only for short profiling runs)")
     ap.add_argument("--workload", choices=["large_sparse", "mpc_batch", "portfolio", "serve"],
                     default="large_sparse")
-    ap.add_argument("--requests", type=int, default=1000, help="requests of the served stream")
+    ap.add_argument("--requests", type=int, default=200, help="requests of the served stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="arrivals per second of the served stream")
     ap.add_argument("--lanes", type=int, default=2, help="server lanes for diagonal-Q requests")
     ap.add_argument("--general-lanes", type=int, default=2, help="server lanes for non-diagonal-Q requests")
