@@ -757,7 +757,7 @@ int resident_per_cu(int which)
 
 #define PDHCG_BATCH_SHAPES(X) \
     X(512, 8192, 1) X(256, 6144, 1) X(256, 2048, 1) X(256, 2048, 4) X(128, 1536, 1) X(128, 1536, 4) X(64, 1536, 1) \
-    X(64, 1024, 4) X(1024, 12288, 1) X(256, 3072, 4) X(256, 3840, 4)
+    X(64, 1024, 4) X(1024, 12288, 1) X(256, 3072, 4) X(256, 3840, 4) X(256, 4608, 4) X(256, 4992, 4)
 
 const BatchShape* batch_shapes(int* count)
 {
