@@ -237,7 +237,7 @@ struct BatchShape {
 };
 // the table of compiled shapes (*count entries)
 const BatchShape* batch_shapes(int* count);
-constexpr int BATCH_SHAPE_DEFAULT = 1;           // 256 threads, 6144 doubles
+constexpr int BATCH_SHAPE_DEFAULT = 12;          // 256 threads, 4992 doubles, 4 waves per SIMD
 constexpr int BATCH_SHAPE_GENERAL_DEFAULT = 8;   // 1024 threads, 12288 doubles (inner solves)
 
 struct BatchOut {

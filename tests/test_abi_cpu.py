@@ -258,7 +258,7 @@ def test_batch_shape_table_and_schedule_validation():
     ns = P.qp_batch_num_shapes()
     assert ns >= 2
     shapes = [P.qp_batch_shape_info(i) for i in range(ns)]
-    assert shapes[1] == (256, 6144, 1)   # the default shape
+    assert shapes[P.qp_batch_default_shape(False)] == (256, 4992, 4)   # the default shape
     for t, l_, w in shapes:
         # whole wavefronts; staged operands leave room in the 160 KiB of LDS;
         # 1..8 waves per SIMD
@@ -280,6 +280,6 @@ def test_batch_shape_table_and_schedule_validation():
         assert L.qp_server_create(C.byref(bad), None, C.byref(h)) == P.ERR_INVALID_ARG
     c = P.qp_server_config_default()
     assert c.batch_shape == -1 and c.batch_order == -1 and c.general_shape == -1 and c.diag_workers == -1
-    assert P.qp_batch_default_shape(False) == 1
+    assert P.qp_batch_default_shape(False) == 12
     g = P.qp_batch_default_shape(True)
     assert 0 <= g < ns and P.qp_batch_shape_info(g)[0] >= 512
