@@ -1517,7 +1517,7 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
     const qp_params dp = qp_params_default();
     if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemsetAsync failed"));
-    if (launch_batch_norm(B, BATCH_SHAPE_DEFAULT, B.roff, B.voff, B.arp, B.acol, B.aval, B.trp, B.tcol, B.tval, nullptr,
+    if (launch_batch_norm(B, BATCH_SHAPE_NORM, B.roff, B.voff, B.arp, B.acol, B.aval, B.trp, B.tcol, B.tval, nullptr,
                           dp.power_tol, dp.power_max_iter, B.x, B.y, B.xt, dnorm, bt->stream) != hipSuccess ||
         hipStreamSynchronize(bt->stream) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "norm kernel failed"));
@@ -1531,7 +1531,7 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
         if ((rc = bupload(bt, &dsel, qgen.data(), (size_t)count))) return bail(rc);
         B.qgen = dsel;
         if (hipMemsetAsync(B.queue, 0, sizeof(int), bt->stream) != hipSuccess ||
-            launch_batch_norm(B, BATCH_SHAPE_DEFAULT, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
+            launch_batch_norm(B, BATCH_SHAPE_NORM, B.voff, B.voff, B.qrp, B.qcol, B.qval, B.qrp, B.qcol, B.qval, dsel,
                               dp.power_tol, dp.power_max_iter, B.x, B.xa, B.xt, dnorm, bt->stream) != hipSuccess ||
             hipStreamSynchronize(bt->stream) != hipSuccess ||
             copy_wait(normq_raw.data(), dnorm, sizeof(double) * count, hipMemcpyDeviceToHost, bt->stream) != hipSuccess)

@@ -238,6 +238,10 @@ struct BatchShape {
 // the table of compiled shapes (*count entries)
 const BatchShape* batch_shapes(int* count);
 constexpr int BATCH_SHAPE_DEFAULT = 12;          // 256 threads, 4992 doubles, 4 waves per SIMD
+// the per-instance norm kernel's shape (its values do not depend on the LDS
+// size, and 3 workgroups per CU measured faster than 4: 99 against 153 ms
+// for the 4096-instance MPC batch)
+constexpr int BATCH_SHAPE_NORM = 1;
 constexpr int BATCH_SHAPE_GENERAL_DEFAULT = 8;   // 1024 threads, 12288 doubles (inner solves)
 
 struct BatchOut {
