@@ -1,0 +1,57 @@
+"""Host-side logic of bench.py: the algorithmic byte counts behind the
+roofline figures, the bound-storage rule they mirror, and the one-GPU guard."""
+
+import subprocess
+import sys
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2602_23967_amd import instances as I  # noqa: E402
+
+
+def _qp(lb, ub, n=6):
+    return I.QP(n=n, m=1, Q=None, A=sp.csr_matrix(np.ones((1, n))), c=np.zeros(n), b=np.zeros(1),
+                sense=b"E", lb=np.asarray(lb, dtype=float), ub=np.asarray(ub, dtype=float))
+
+
+def test_bound_bytes_rule():
+    # one shared pair: nothing per variable
+    assert bench.bound_bytes(_qp([0.0] * 6, [10.0] * 6)) == 0
+    # a few distinct pairs: a class byte per variable
+    assert bench.bound_bytes(_qp([0, 0, -1, -1, -np.inf, 0], [1, 1, 1, 1, np.inf, 1])) == 1
+    # more than 256 distinct pairs: two FP64 arrays
+    n = 300
+    assert bench.bound_bytes(_qp(-np.arange(n, dtype=float), np.ones(n), n=n)) == 16
+    # -0.0 and 0.0 are different bit patterns, so different classes
+    assert bench.bound_bytes(_qp([0.0, -0.0], [1.0, 1.0], n=2)) == 1
+
+
+def test_hp_bytes_counts():
+    n, nnz = 1000, 11000
+    # 12 B per nonzero, int32 row pointers, p gathered once, g and x read,
+    # H p written, the box by its storage
+    assert bench.hp_bytes(n, nnz, 0) == 12 * nnz + 4 * (n + 1) + 8 * n * 4
+    assert bench.hp_bytes(n, nnz, 16) - bench.hp_bytes(n, nnz, 0) == 16 * n
+    # the large sparse instance's figure quoted in the design notes
+    assert bench.hp_bytes(1_000_000, 10_999_950, 0) == 167_999_404
+
+
+def test_batch_bytes_counts():
+    q = I.mpc(0)
+    per = bench.batch_bytes(q, 1, 6, 1)
+    assert per == 2 * 6 * q.nnz_A + 4 * (q.n + q.m + 2) + 8 * q.n * 10 + 1 * q.n + 8 * q.m * 6
+    assert bench.batch_bytes(q, 7, 6, 1) == 7 * per
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
