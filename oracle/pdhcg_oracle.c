@@ -26,7 +26,9 @@
  *       Halpern / PID / tolerance trajectory: parity unpinned (the paper
  *       prints no trace); only their algebra on hand values is pinned
  *   KKT residuals r_primal, r_dual, r_gap ........... Section 4
- *       pinned by an independent NumPy evaluation and by exact solutions
+ *       pinned by exact solutions (all three vanish) and by hand-worked exact
+ *       values with nonzero numerators, each term of the r_dual and r_gap
+ *       denominators dominating in turn
  *   primal / dual infeasibility certificates ........ Section 5
  *       pinned by constructed infeasible / unbounded instances with known rays
  *   final solutions ............................... dense KKT solves,

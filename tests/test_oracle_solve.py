@@ -294,3 +294,37 @@ def test_factored_portfolio_equals_factor_variable_form():
     assert a.status == b.status == oracle.OPTIMAL
     assert a.info["primal_obj"] == pytest.approx(b.info["primal_obj"], rel=1e-7, abs=1e-9)
     assert np.abs(a.x - b.x[:400]).max() <= 1e-5
+
+
+def _hand_case_qp(c):
+    import scipy.sparse as sp
+    return I.QP(n=3, m=2, Q=sp.csr_matrix(np.diag([4.0, 3.0, 0.0])),
+                A=sp.csr_matrix(np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 1.0]])),
+                c=np.array(c, dtype=np.float64), b=np.array([2.0, 1.0]), sense=b"EG",
+                lb=np.array([-1.0, -np.inf, -np.inf]), ub=np.array([np.inf, 2.0, np.inf]),
+                name="kkt_hand")
+
+
+def _hand_cases():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "kkt_hand_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _hand_cases(), ids=lambda c: c["name"])
+def test_kkt_normalisations_match_hand_worked_values(case):
+    """Section 4's three residuals with nonzero numerators, each denominator
+    term of r_dual (||Qx||, ||A'y||, ||c||) and of r_gap (|primal objective|,
+    |x'Qx/2 + p(-rhat) + p(y)|, either sign) made to dominate in turn, on a
+    3-variable problem with a lower-bounded, an upper-bounded and a free
+    variable, against exact rationals worked by hand (the derivation is in
+    the fixture).  A 2-norm in place of an infinity norm, a dropped term, a
+    missing absolute value or the gap taken at r instead of proj_R(r) fails
+    at least one case."""
+    from fractions import Fraction
+    q = _hand_case_qp(case["c"])
+    k = oracle.kkt(q, np.array([1.0, 1.0, 0.5]), np.array(case["y"], dtype=np.float64))
+    for key in ("r_primal", "r_dual", "r_gap", "pobj", "dobj", "natural", "pviol"):
+        want = float(Fraction(case[key]))
+        assert k[key] == pytest.approx(want, rel=1e-14, abs=1e-300), key
