@@ -274,6 +274,44 @@ int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds);
 
 void qp_batch_destroy(qp_batch* bt);
 
+/* ---- batched solve without device allocation ---------------------------
+ *
+ * For callers that cannot allocate device memory: tight serving loops and
+ * harnesses that forbid hipMalloc.  One blocking call solves a batch exactly
+ * as qp_batch_create + qp_batch_solve + qp_batch_result would (same
+ * arguments and validation, same kernels, default launch schedule: the
+ * results are bitwise those of the allocating path), but every device buffer
+ * of the batch -- the copied problem, the iterates and anchors, the work
+ * counter and the outcome records -- is carved from one static workspace of
+ * QP_STATIC_WORKSPACE_BYTES that the library holds on each device it runs on
+ * until the process ends.  Nothing is allocated or freed on the device, and
+ * no stream or event is created: the call runs on `stream` (a hipStream_t of
+ * the current device; NULL is the null stream) and waits for it.
+ *
+ * Inputs as qp_batch_create (host buffers, copied; the caller may free them
+ * on return); params as qp_batch_solve (NULL = defaults).  Outputs (host,
+ * each may be NULL): x (all n variables) and y (all m rows), packed like the
+ * problem, with the conventions of qp_batch_result (certificates in place of
+ * the iterates for infeasible instances); status[count]; info[count].
+ * Returns the number of OPTIMAL instances, or QP_ERR_INVALID_ARG (bad input,
+ * or a batch whose device copy does not fit the workspace: the message gives
+ * the limit), QP_ERR_DEVICE.
+ *
+ * The workspace keeps the last call's contents; every buffer a call reads is
+ * written by that call first.  Calls on one device share the workspace: the
+ * library serialises calls from the threads of one process (each holds the
+ * device's workspace until its results are copied out); work that another
+ * agent (another library instance in the process, or a caller writing the
+ * workspace) overlaps with a call races. */
+#define QP_STATIC_WORKSPACE_BYTES (64ll << 20)
+
+int qp_batch_solve_static(int64_t count, const int64_t* var_off, const int64_t* row_off,
+                          const int64_t* Q_rowptr, const int32_t* Q_col, const double* Q_val,
+                          const int64_t* A_rowptr, const int32_t* A_col, const double* A_val,
+                          const double* c, const double* b, const char* sense,
+                          const double* lb, const double* ub, const qp_params* params, void* stream,
+                          double* x, double* y, int32_t* status, qp_info* info);
+
 /* ---- launch schedule of the batched solve, and its autotuner -------------
  *
  * One workgroup solves one instance; the schedule is the workgroup shape

@@ -131,6 +131,9 @@ def lib():
         L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
+        L.qp_batch_solve_static.argtypes = [_i64, _lp, _lp, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp,
+                                            C.c_char_p, _dp, _dp, C.POINTER(QPParams), C.c_void_p,
+                                            _dp, _dp, _ip, C.POINTER(QPInfo)]
         L.qp_measure_gather_rate.argtypes = [_i64, _i64, C.c_int32, _dp]
         L.qp_batch_num_shapes.argtypes = []
         L.qp_batch_default_shape.argtypes = [C.c_int32]
@@ -394,6 +397,32 @@ def qp_batch_destroy(h):
     if h is not None and h.value:
         lib().qp_batch_destroy(h)
         h.value = None
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20   # QP_STATIC_WORKSPACE_BYTES
+
+
+def qp_batch_solve_static(count, var_off, row_off, Q, A, c, b, sense: bytes, lb=None, ub=None,
+                          params: QPParams | None = None, stream=None):
+    """One blocking batched solve whose device memory is the library's
+    static workspace (qp_batch_solve_static).  Returns (number of OPTIMAL
+    instances, x, y, status per instance, info dict per instance)."""
+    vo = np.ascontiguousarray(var_off, dtype=np.int64)
+    ro = np.ascontiguousarray(row_off, dtype=np.int64)
+    qp_, qj_, qv_, keepq = _csr(Q)
+    ap_, aj_, av_, keepa = _csr(A) if A is not None else (None, None, None, ())
+    c, b, lb, ub = _f64(c), _f64(b), _f64(lb), _f64(ub)
+    n, m = int(vo[count]), int(ro[count])
+    x = np.zeros(n)
+    y = np.zeros(max(m, 1))
+    st = np.zeros(count, dtype=np.int32)
+    infos = (QPInfo * count)()
+    s_ = None if stream is None else C.c_void_p(stream)
+    opt = _check(lib().qp_batch_solve_static(count, vo.ctypes.data_as(_lp), ro.ctypes.data_as(_lp), qp_, qj_,
+                                             qv_, ap_, aj_, av_, _d(c), _d(b), sense, _d(lb), _d(ub),
+                                             None if params is None else C.byref(params), s_, _d(x), _d(y),
+                                             st.ctypes.data_as(_ip), infos))
+    return opt, x, y[:m], st, [infos[i].as_dict() for i in range(count)]
 
 
 def qp_batch_num_shapes() -> int:

@@ -1261,6 +1261,7 @@ struct qp_batch {
     int64_t nnz_a = 0, nnz_q = 0;
     float *a32 = nullptr, *t32 = nullptr, *q32 = nullptr;   // made at the first mixed solve
     std::vector<void*> allocs;
+    Arena* arena = nullptr;        // set: device buffers come from the caller's region (none freed)
     std::vector<BatchOut> out;
     std::vector<double> norm_A;
     // launch schedule: shape (index into the compiled table) and queue order
@@ -1278,6 +1279,15 @@ int balloc(qp_batch* bt, T** p, size_t count)
 {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (Arena* a = bt->arena) {
+        const size_t at = (a->used + 255) & ~(size_t)255;
+        if (at > a->cap || bytes > a->cap - at)
+            return fail(QP_ERR_INVALID_ARG, "the batch needs more device memory than the static workspace's " +
+                                                std::to_string(a->cap) + " bytes");
+        a->used = at + bytes;
+        *p = reinterpret_cast<T*>(a->base + at);
+        return 0;
+    }
     hipError_t e = hipMallocAsync(&q, bytes, bt->stream);
     if (e != hipSuccess) return fail(QP_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
     bt->allocs.push_back(q);
@@ -1303,7 +1313,7 @@ extern "C" {
 void qp_batch_destroy(qp_batch* bt)
 {
     if (!bt) return;
-    if (bt->stream) {
+    if (bt->stream || bt->arena) {
         (void)hipStreamSynchronize(bt->stream);
         for (void* p : bt->allocs) (void)hipFreeAsync(p, bt->stream);
         (void)hipStreamSynchronize(bt->stream);
@@ -1331,7 +1341,7 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
                  const int64_t* Qp, const int32_t* Qj, const double* Qv,
                  const int64_t* Ap, const int32_t* Aj, const double* Av,
                  const double* c, const double* b, const char* sense,
-                 const double* lb, const double* ub, qp_batch** out)
+                 const double* lb, const double* ub, qp_batch** out, Arena* arena)
 {
     const double t0 = now_s();
     if (!out) return fail(QP_ERR_INVALID_ARG, "out is NULL");
@@ -1416,14 +1426,16 @@ int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const 
     bt->m = m;
     bt->voff.assign(var_off, var_off + count + 1);
     bt->roff.assign(row_off, row_off + count + 1);
-    if (lane) {
+    bt->arena = arena;
+    if (lane || arena) {
         bt->stream = lane;
         bt->own_stream = false;
     } else if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) {
         return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
     }
-    if (hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(QP_ERR_DEVICE, "hipStreamCreate failed"));
+    // without an event (arena mode) the batch waits on its stream instead
+    if (!arena && hipEventCreateWithFlags(&bt->done, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(QP_ERR_DEVICE, "hipEventCreate failed"));
     BatchDev& B = bt->B;
     B.count = (int)count;
     std::vector<int> vo32(count + 1), ro32(count + 1), arp32(m + 1);
@@ -1610,14 +1622,14 @@ int batch_launch(qp_batch* bt, const qp_params* params)
     HIPCHK(hipMemsetAsync(bt->B.queue, 0, sizeof(int), bt->stream));
     bt->B.order = bt->order ? bt->dorder : nullptr;
     HIPCHK(launch_batch_solve(bt->B, P, bt->shape, bt->stream));
-    HIPCHK(hipEventRecord(bt->done, bt->stream));
+    if (bt->done) HIPCHK(hipEventRecord(bt->done, bt->stream));
     return 0;
 }
 
 // 1 when the launched solve has finished, 0 while it runs, < 0 on error
 int batch_poll(qp_batch* bt)
 {
-    const hipError_t q = hipEventQuery(bt->done);
+    const hipError_t q = bt->done ? hipEventQuery(bt->done) : hipStreamQuery(bt->stream);
     if (q == hipSuccess) return 1;
     if (q == hipErrorNotReady) return 0;
     return fail(QP_ERR_DEVICE, std::string("batch solve failed: ") + hipGetErrorString(q));
@@ -1679,7 +1691,7 @@ int batch_results_all(qp_batch* bt, std::vector<double>& x, std::vector<double>&
 // returns the number of OPTIMAL instances
 int batch_finish(qp_batch* bt)
 {
-    HIPCHK(hipEventSynchronize(bt->done));
+    HIPCHK(bt->done ? hipEventSynchronize(bt->done) : hipStreamSynchronize(bt->stream));
     bt->solve_seconds = now_s() - bt->t_launch;
     bt->out.resize(bt->count);
     HIPCHK(copy_wait(bt->out.data(), bt->B.out, sizeof(BatchOut) * bt->count, hipMemcpyDeviceToHost, bt->stream));

@@ -22,12 +22,23 @@ int check_symmetric(int64_t n, const int64_t* rp, const int32_t* cj, const doubl
 int check_vec(const char* name, int64_t len, const double* v, bool allow_inf);
 int check_bounds(const char* name, int64_t len, const double* l, const double* u);
 
-// qp_batch_create on a stream lent by the caller (NULL: the batch makes its own)
+// A region of device memory the library does not own (the static workspace of
+// qp_batch_solve_static): allocations are carved from it in 256-byte steps
+// and never freed; one that does not fit fails with QP_ERR_INVALID_ARG.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+};
+
+// qp_batch_create on a stream lent by the caller (NULL: the batch makes its
+// own).  With an arena, every device buffer of the batch comes from it, the
+// batch uses `lane` as given (NULL is the null stream) and creates no stream
+// or event: nothing is allocated on the device.
 int batch_create(hipStream_t lane, int64_t count, const int64_t* var_off, const int64_t* row_off,
                  const int64_t* Qp, const int32_t* Qj, const double* Qv,
                  const int64_t* Ap, const int32_t* Aj, const double* Av,
                  const double* c, const double* b, const char* sense,
-                 const double* lb, const double* ub, qp_batch** out);
+                 const double* lb, const double* ub, qp_batch** out, Arena* arena = nullptr);
 
 // asynchronous batched solve: launch on the batch's stream, poll
 // (1 finished, 0 running, < 0 error), finish (fetches the outcomes and

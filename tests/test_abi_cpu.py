@@ -157,6 +157,20 @@ def test_no_device_gives_device_error_or_success():
         P.qp_destroy(h)
 
 
+def test_static_batch_without_a_device():
+    """The allocation-free batched solve needs a device: without one it
+    reports QP_ERR_DEVICE (with one, it solves)."""
+    qs = [I.tiny_lp(1), I.tiny_lp(2)]
+    big, vo, ro = I.pack(qs)
+    try:
+        opt, x, y, st, infos = P.qp_batch_solve_static(len(qs), vo, ro, big.Q, big.A, big.c, big.b, big.sense,
+                                                       big.lb, big.ub)
+    except P.QPError as e:
+        assert e.code == P.ERR_DEVICE
+    else:
+        assert len(st) == 2 and x.shape == (big.n,)
+
+
 def test_batch_validation_errors():
     from paper_2602_23967_amd.instances import pack
     qs = [I.mpc(i, horizon=10) for i in range(3)]
