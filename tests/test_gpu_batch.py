@@ -1,6 +1,10 @@
 """Batched solve (many QPs with diagonal Q in one persistent launch) against
 the oracle, instance by instance, through the C ABI."""
 
+import json
+import os
+import time
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -125,6 +129,42 @@ def test_batch_many_instances(torch):
             g = bs.result(i)
             k = oracle.kkt(qs[i], g.x, g.y)
             assert max(k["r_primal"], k["r_dual"], k["r_gap"]) <= 1e-6
+
+
+def test_mpc_batch_full_size_against_oracle(torch):
+    """The 4096-instance MPC batch at full size, in mixed precision (its
+    configuration) and FP64: every instance OPTIMAL with relative KKT <= 1e-6
+    evaluated by the oracle on its returned point, and on the seeded 5 %
+    sample the oracle solved at tol 1e-9 (stored:
+    tests/golden/oracle_mpc_sample.json) the oracle's status and objective
+    to 1e-6 (1 + |f|)."""
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_mpc_sample.json")) as f:
+        gold = json.load(f)
+    t = time.perf_counter()
+    qs = [I.mpc(i) for i in range(4096)]
+    print(f"generated 4096 MPC instances in {time.perf_counter() - t:.1f}s", flush=True)
+    sample = {r["index"]: r for r in gold["results"]}
+    with P.BatchSolver(qs) as bs:
+        for prec in (P.PRECISION_MIXED, P.PRECISION_FP64):
+            st, secs = bs.solve(precision=prec)
+            print(f"precision {prec}: 4096 instances in {secs * 1e3:.1f} ms, "
+                  f"{int(np.sum(st == P.OPTIMAL))} optimal", flush=True)
+            assert np.all(st == P.OPTIMAL)
+            worst_kkt = worst_obj = 0.0
+            for i, q in enumerate(qs):
+                g = bs.result(i)
+                k = oracle.kkt(q, g.x, g.y)
+                worst_kkt = max(worst_kkt, k["r_primal"], k["r_dual"], k["r_gap"])
+                assert np.all(g.x >= q.lb) and np.all(g.x <= q.ub), q.name
+                if i in sample:
+                    r = sample[i]
+                    assert r["instance"] == q.name and g.status == r["status"], (q.name, r["status_name"])
+                    err = abs(g.info["primal_obj"] - r["primal_obj"]) / (1 + abs(r["primal_obj"]))
+                    worst_obj = max(worst_obj, err)
+            print(f"precision {prec}: worst relative KKT {worst_kkt:.2e} over 4096 instances; worst objective "
+                  f"error {worst_obj:.2e} over the {len(sample)}-instance oracle sample", flush=True)
+            assert worst_kkt <= 1e-6
+            assert worst_obj <= 1e-6
 
 
 def test_batch_general_q_matches_single_path(torch):
