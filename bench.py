@@ -62,34 +62,129 @@ def hp_bytes(n, nnz_q, bb=16):
     return 12 * nnz_q + 4 * (n + 1) + 8 * n * 4 + bb * n
 
 
-def cpu_baseline(q, gpu_units_per_solve, sample_iters):
-    """The oracle on the host cores: setup alone (max_iter = 0), then the
-    first `sample_iters` outer iterations; the per-iteration cost (outer
-    plus inner iterations counted as equal units) is scaled to one full
-    solve with the GPU's unit count (setup excluded on both sides)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(q, gpu_info, sample_iters, tol):
+    """The oracle on the host cores, on a bounded sample: its first
+    `sample_iters` outer iterations (with their inner solves and the check
+    that ends the sample).  The oracle times its phases; the cost of one
+    outer step (inner solve excluded), one inner step and one check is each
+    applied to the GPU run's counts, so the estimate follows the full
+    solve's mix of outer and inner steps (setup -- the norm estimates --
+    excluded on both sides)."""
     import oracle
 
     t = time.perf_counter()
-    oracle.solve(q, max_iter=0)
-    t0 = time.perf_counter() - t
-    log(f"oracle setup {t0:.1f}s")
-    t = time.perf_counter()
-    r = oracle.solve(q, max_iter=sample_iters)
-    t1 = time.perf_counter() - t
-    units = r.info["iterations"] + r.info["inner_iterations"]
-    per_unit = max(t1 - t0, 1e-9) / max(units, 1)
-    est = per_unit * gpu_units_per_solve
-    log(f"oracle sample {t1:.1f}s, {r.info['iterations']} outer + {r.info['inner_iterations']} inner")
+    r = oracle.solve(q, tol=tol, max_iter=sample_iters)
+    wall = time.perf_counter() - t
+    i = r.info
+    per_inner = i["seconds_inner"] / max(i["inner_iterations"], 1)
+    per_check = i["seconds_check"] / max(i["checks"], 1)
+    per_outer = (i["seconds_total"] - i["seconds_setup"] - i["seconds_inner"] - i["seconds_check"]) / max(
+        i["iterations"], 1)
+    go, gi, gc = gpu_info["iterations"], gpu_info["inner_iterations"], gpu_info["checks"]
+    est = per_outer * go + per_inner * gi + per_check * gc
+    log(f"oracle sample {wall:.1f}s: {i['iterations']} outer ({per_outer * 1e3:.2f} ms each), "
+        f"{i['inner_iterations']} inner ({per_inner * 1e3:.2f} ms each), {i['checks']} checks "
+        f"({per_check * 1e3:.1f} ms each); full-solve estimate {est:.1f}s")
     return {
         "value": 1.0 / est,
         "unit": "QPs solved/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"oracle_qp_solve on the same instance for the first {sample_iters} outer "
-                   f"iterations ({r.info['iterations']} outer + {r.info['inner_iterations']} inner "
-                   f"in {t1 - t0:.2f}s beyond its {t0:.2f}s setup); per-iteration time scaled to "
-                   f"the GPU run's {gpu_units_per_solve} outer+inner iterations per solve"),
+        "cpu_model": cpu_model(),
+        "method": "phase costs of a bounded sample applied to the GPU run's step counts",
+        "sample": (f"oracle_qp_solve on the same instance for its first {i['iterations']} outer iterations "
+                   f"({i['inner_iterations']} inner, {i['checks']} checks) in {wall:.2f}s, "
+                   f"{i['seconds_setup']:.2f}s of it setup; per outer step {per_outer * 1e3:.3f} ms, per inner "
+                   f"step {per_inner * 1e3:.3f} ms, per check {per_check * 1e3:.2f} ms, applied to "
+                   f"{go} outer + {gi} inner steps + {gc} checks"),
     }
+
+
+def cpu_small(q, tol, budget_s=10.0):
+    """Whole oracle solves of a small instance, repeated for about budget_s
+    on all host threads and again on one thread."""
+    import oracle
+    nth = oracle.num_threads()
+    res = {}
+    for threads in (nth, 1):
+        oracle.set_num_threads(threads)
+        t = time.perf_counter()
+        k = 0
+        while k == 0 or time.perf_counter() - t < budget_s / 2:
+            oracle.solve(q, tol=tol)
+            k += 1
+        res[threads] = (k, time.perf_counter() - t)
+    oracle.set_num_threads(nth)
+    (k, el), (k1, el1) = res[nth], res[1]
+    return {"value": k / el, "unit": "QPs solved/s", "cores": nth, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{k} whole oracle_qp_solve runs of the same instance in {el:.2f}s",
+            "single_thread": {"value": k1 / el1, "cores": 1,
+                              "sample": f"{k1} whole runs in {el1:.2f}s"}}
+
+
+def cpu_full(workload, tol, budget_s, threads=0):
+    """The oracle's whole solve of a workload, run in a child process under
+    its own time budget (a run past the budget is reported as a timeout)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-child", workload, "--tol", repr(tol)]
+    env = dict(os.environ)
+    if threads > 0:
+        env["OMP_NUM_THREADS"] = str(threads)
+    t = time.perf_counter()
+    try:
+        p = subprocess.run(cmd, capture_output=True, text=True, timeout=budget_s, env=env)
+    except subprocess.TimeoutExpired:
+        return {"timeout_s": budget_s, "kind": "oracle", "cpu_model": cpu_model()}
+    el = time.perf_counter() - t
+    if p.returncode != 0:
+        raise RuntimeError(f"oracle child failed: {p.stderr[-2000:]}")
+    res = json.loads(p.stdout.strip().splitlines()[-1])
+    res.update({"kind": "oracle", "cpu_model": cpu_model(), "child_wall_s": el})
+    return res
+
+
+def oracle_child(workload, tol):
+    """Body of the child process of cpu_full: generate, solve, print JSON."""
+    import oracle
+    from paper_2602_23967_amd import instances as I
+    if workload == "large_sparse":
+        qs = [I.large_sparse(0)]
+    elif workload == "small":
+        qs = [I.random_small(0)]
+    elif workload == "portfolio":
+        qs = [I.portfolio(0)]
+    elif workload == "mpc_batch":
+        qs = [I.mpc(i) for i in range(4096)]
+    else:
+        raise SystemExit(f"no oracle child for {workload}")
+    t = time.perf_counter()
+    st, it, inner, objs = [], 0, 0, []
+    for q in qs:
+        r = oracle.solve(q, tol=tol)
+        st.append(r.status)
+        it += r.info["iterations"]
+        inner += r.info["inner_iterations"]
+        objs.append(r.info["primal_obj"])
+    el = time.perf_counter() - t
+    out = {"workload": workload, "instances": len(qs), "seconds": el, "value": len(qs) / el,
+           "unit": "QPs solved/s", "cores": oracle.num_threads(),
+           "optimal": int(sum(s_ == oracle.OPTIMAL for s_ in st)), "iterations": it,
+           "inner_iterations": inner}
+    if len(qs) == 1:
+        out["status"] = oracle.STATUS_NAMES[st[0]]
+        out["primal_obj"] = objs[0]
+    print(json.dumps(out), flush=True)
 
 
 def batch_bytes(q, iters, vb=12, bb=16):
@@ -166,9 +261,13 @@ def main_batch(args, torch, P, I):
         with P.Solver(q) as s1:
             r = s1.solve(p64)
             one.append(r.info["solve_seconds"])
+    # solved: OPTIMAL with the solver's own KKT at the tolerance (the tests
+    # check these points with the oracle's KKT evaluation)
+    n_ok = sum(1 for i in infos if i["status"] == P.OPTIMAL and
+               max(i["r_primal"], i["r_dual"], i["r_gap"]) <= args.tol)
     out = {
         "metric": METRIC,
-        "value": len(qs) * args.steps / elapsed,
+        "value": n_ok * args.steps / elapsed,
         "unit": "QPs solved/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps,
@@ -179,6 +278,7 @@ def main_batch(args, torch, P, I):
                                f"{'mixed precision' if mixed else 'FP64'}",
                    "instances": len(qs)},
         "solved": bool(np.all(st == P.OPTIMAL)),
+        "solved_count": int(n_ok),
         "iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
         "roofline": {"bound": "hbm", "achieved": nbytes / kernel_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -189,15 +289,26 @@ def main_batch(args, torch, P, I):
     }
     if not args.no_cpu_baseline:
         import oracle
-        t = time.perf_counter()
-        ns = 0
-        while ns < len(qs) and time.perf_counter() - t < 10.0:
-            oracle.solve(qs[ns], tol=args.tol)
-            ns += 1
-        el = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": ns / el, "unit": "QPs solved/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": f"oracle_qp_solve on the first {ns} instances, one at a time ({el:.1f}s)"}
+        nth = oracle.num_threads()
+        runs = {}
+        for threads, budget in ((nth, 15.0), (1, 10.0)):
+            oracle.set_num_threads(threads)
+            t = time.perf_counter()
+            ns = 0
+            while ns < len(qs) and time.perf_counter() - t < budget:
+                oracle.solve(qs[ns], tol=args.tol)
+                ns += 1
+            runs[threads] = (ns, time.perf_counter() - t)
+        oracle.set_num_threads(nth)
+        ns, el = runs[nth]
+        ns1, el1 = runs[1]
+        out["cpu_baseline"] = {"value": ns / el, "unit": "QPs solved/s", "cores": nth, "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"oracle_qp_solve on the first {ns} instances, one at a time ({el:.1f}s)",
+                               "single_thread": {"value": ns1 / el1, "cores": 1,
+                                                 "sample": f"the first {ns1} instances ({el1:.1f}s)"}}
+    if args.cpu_full:
+        out["cpu_full_solve"] = cpu_full("mpc_batch", args.tol, args.cpu_budget_s)
     print(json.dumps(out), flush=True)
 
 
@@ -291,7 +402,9 @@ def main_portfolio(args, torch, P, I):
                           "x_inf": float(np.abs(x - x64).max())},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(q, infos[-1]["iterations"], args.cpu_sample_iters)
+        out["cpu_baseline"] = cpu_baseline(q, infos[-1], args.cpu_sample_iters or 4096, args.tol)
+    if args.cpu_full:
+        out["cpu_full_solve"] = cpu_full("portfolio", args.tol, args.cpu_budget_s)
     print(json.dumps(out), flush=True)
 
 
@@ -362,7 +475,7 @@ def main_serve(args, torch, P, I):
         n_one += 1
     out = {
         "metric": METRIC,
-        "value": len(qs) / (last - first),
+        "value": int(np.sum(ok)) / (last - first),
         "unit": "QPs solved/s",
         "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": 1e3 * elapsed,
@@ -393,7 +506,7 @@ def main():
     ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
     ap.add_argument("--max-iter", type=int, default=100000,
                     help="outer iteration cap (lower only for short profiling runs)")
-    ap.add_argument("--workload", choices=["large_sparse", "mpc_batch", "portfolio", "serve"],
+    ap.add_argument("--workload", choices=["large_sparse", "small", "mpc_batch", "portfolio", "serve"],
                     default="large_sparse")
     ap.add_argument("--requests", type=int, default=200, help="requests of the served stream")
     ap.add_argument("--rate", type=float, default=2000.0, help="arrivals per second of the served stream")
@@ -422,8 +535,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 64 MiB (scale for rocprofv3 byte counters)")
-    ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    ap.add_argument("--cpu-sample-iters", type=int, default=None,
+                    help="outer iterations of the oracle's timed sample (default: per workload)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle's whole solve (child process, --cpu-budget-s)")
+    ap.add_argument("--cpu-budget-s", type=float, default=900.0)
+    ap.add_argument("--oracle-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.oracle_child:
+        return oracle_child(args.oracle_child, args.tol)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -463,7 +584,8 @@ def main():
         return main_serve(args, torch, P, I)
 
     t = time.perf_counter()
-    q = I.large_sparse(0, n=args.n)
+    small = args.workload == "small"
+    q = I.random_small(0) if small else I.large_sparse(0, n=args.n)
     log(f"generated {q.name}: n={q.n} m={q.m} nnz(Q)={q.nnz_Q} nnz(A)={q.nnz_A} "
         f"in {time.perf_counter() - t:.1f}s")
     h = P.qp_create_from(q)
@@ -515,7 +637,6 @@ def main():
         if tj:
             kern[name] = {"avg_us": round(1e3 * sum(i["fam_ms"][j] for i in infos) / tj, 3),
                           "launches_per_solve": infos[-1]["fam_launches"][j]}
-    units = infos[-1]["iterations"] + infos[-1]["inner_iterations"]
     # the product's random gathers (one per nonzero) against the device's
     # measured gather rate for the same vector length and part keying: the
     # bound this product actually meets (outside the timed region)
@@ -542,8 +663,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"large sparse convex QP n={q.n} m={q.m} (half '=', half '>='), "
-                               f"Q SPD ~10 off-diagonals/row, A 8 nnz/row, box [0,10], tol {args.tol:g}",
+        "config": {"workload": (f"tiny random convex QP n={q.n} m={q.m} (half '=', half '>='), "
+                                f"Q = B'B + 0.01 I, A at 1%, box [-1,1], tol {args.tol:g}") if small else
+                               (f"large sparse convex QP n={q.n} m={q.m} (half '=', half '>='), "
+                                f"Q SPD ~10 off-diagonals/row, A 8 nnz/row, box [0,10], tol {args.tol:g}"),
                    "n": q.n, "m": q.m, "nnz_Q": q.nnz_Q, "nnz_A": q.nnz_A, "tol": args.tol},
         "solved": solved,
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -552,15 +675,32 @@ def main():
                        "inner_per_s": infos[-1]["inner_iterations"] / np.median(lat)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-                     "kernel": "inner H p product (k_spmv<EpiStepA> + k_rows<EpiStepA>)",
+                     "kernel": ("inner H p product (k_spmv<EpiStepA>)" if small else
+                                "inner H p product (k_spmv<EpiStepA> + k_rows<EpiStepA>)"),
                      "bytes_per_launch": nbytes, "avg_us": avg_us, "timed_launches": timed,
                      "launches": launches, "active_launches": active},
         "gather_roofline": gather,
         "kernels": kern,
         "setup_s": info["setup_seconds"],
     }
+    if small:
+        # launch-bound: the latency of one iteration is the figure that matters
+        med = float(np.median(lat))
+        fam_us = {k: v["avg_us"] for k, v in kern.items()}
+        out["latency_us"] = {
+            "per_outer_iteration": 1e6 * med / max(infos[-1]["iterations"], 1),
+            "per_inner_step_kernels": sum(fam_us.get(k, 0.0) for k in ("dir", "spmv_hp", "update")),
+            "note": ("per_outer_iteration = solve wall time / outer iterations (inner steps included); "
+                     "per_inner_step_kernels = event-timed main kernels of one inner step (direction, H p, "
+                     "update; finishing kernels and launch gaps not included)")}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(q, units, args.cpu_sample_iters)
+        if small:
+            out["cpu_baseline"] = cpu_small(q, args.tol)
+        else:
+            out["cpu_baseline"] = cpu_baseline(q, infos[-1], args.cpu_sample_iters or 24, args.tol)
+    if args.cpu_full and not small:
+        out["cpu_full_solve"] = cpu_full("large_sparse", args.tol, args.cpu_budget_s)
+        log(f"oracle full solve: {out['cpu_full_solve']}")
     print(json.dumps(out), flush=True)
 
 

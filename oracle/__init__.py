@@ -44,7 +44,9 @@ class Info(C.Structure):
                 ("r_dual", C.c_double), ("r_gap", C.c_double), ("primal_obj", C.c_double),
                 ("dual_obj", C.c_double), ("omega", C.c_double), ("eta", C.c_double),
                 ("norm_A", C.c_double), ("norm_Q", C.c_double), ("eps_inner", C.c_double),
-                ("natural_residual", C.c_double)]
+                ("natural_residual", C.c_double), ("seconds_setup", C.c_double),
+                ("seconds_inner", C.c_double), ("seconds_check", C.c_double),
+                ("seconds_total", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -81,6 +83,8 @@ def lib():
         L.oracle_splitmix_unit.argtypes = [C.c_uint64]
         L.oracle_splitmix_unit.restype = C.c_double
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.argtypes = [C.c_int]
+        L.oracle_set_num_threads.restype = None
         L.oracle_halpern.argtypes = [_i64, _i64, C.c_double, _dp, _dp, _dp, _dp]
         L.oracle_pid.argtypes = [C.c_double] * 7 + [_dp, _dp]
         L.oracle_pid.restype = C.c_double
@@ -240,6 +244,10 @@ def splitmix_unit(i: int) -> float:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
 
 
 def halpern(t, theta, zt, z, za):

@@ -44,11 +44,20 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 
 #define CHUNK 4096
+
+/* wall clock in seconds (phase timings of oracle_info only) */
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    timespec_get(&ts, TIME_UTC);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
 
 int oracle_num_threads(void)
 {
@@ -56,6 +65,15 @@ int oracle_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
@@ -907,6 +925,7 @@ int oracle_qp_solve(int64_t n, int64_t m,
     for (int64_t i = 0; i < n; ++i) if (lv[i] > uv[i]) return -1;
     for (int64_t i = 0; i < m; ++i) if (lc[i] > uc[i]) return -1;
 
+    const double t_call = wall_seconds();
     oprob pr;
     setup_problem(&pr, n, m, Qp, Qj, Qv, Ap, Aj, Av, c, lc, uc, lv, uv);
     oracle_info inf;
@@ -962,11 +981,14 @@ int oracle_qp_solve(int64_t n, int64_t m,
     int status = ORACLE_NOT_SOLVED;
     kkt_t kk;
     memset(&kk, 0, sizeof(kk));
+    inf.seconds_setup = wall_seconds() - t_call;
+    double check_t0 = -1.0;   /* start of the check in progress, if any */
 
     for (;;) {
         if (k > 0 || prm.max_iter == 0) {
             /* ---------------- check ------------------------------------ */
             if (k % prm.check_every == 0 || k >= prm.max_iter) {
+                check_t0 = wall_seconds();
                 inf.checks++;
                 kk = kkt_eval(&pr, xt, yt);
                 double worst = fmax(kk.r_primal, fmax(kk.r_dual, kk.r_gap));
@@ -1007,6 +1029,8 @@ int oracle_qp_solve(int64_t n, int64_t m,
                     R_prev_valid = 0;
                     inf.restarts++;
                 }
+                inf.seconds_check += wall_seconds() - check_t0;
+                check_t0 = -1.0;
             }
         }
         if (k >= prm.max_iter) { status = ORACLE_ITERATION_LIMIT; break; }
@@ -1022,8 +1046,10 @@ int oracle_qp_solve(int64_t n, int64_t m,
             eps = fmax(prm.gamma_inner * r0, prm.eps_min);
         }
         double eps_use = prm.eps_inner_fixed > 0.0 ? prm.eps_inner_fixed : eps;
+        const double t_inner = wall_seconds();
         inf.inner_iterations += solve_subproblem(&pr, prm.inner_solver, inv_tau, rhs, xt,
                                                  eps_use, prm.max_inner, normQ, &prm, NULL);
+        inf.seconds_inner += wall_seconds() - t_inner;
 
         /* ---------------- dual step (eq. extrapolation, dual_update) -------- */
         for (int64_t i = 0; i < n; ++i) xb[i] = 2.0 * xt[i] - x[i];
@@ -1052,6 +1078,7 @@ int oracle_qp_solve(int64_t n, int64_t m,
         if (t == 1) R_start = sqrt(omega * ndx * ndx + ndy * ndy / omega);
     }
 
+    if (check_t0 >= 0.0) inf.seconds_check += wall_seconds() - check_t0;
     inf.status = status;
     inf.iterations = k;
     inf.r_primal = kk.r_primal; inf.r_dual = kk.r_dual; inf.r_gap = kk.r_gap;
@@ -1072,5 +1099,6 @@ int oracle_qp_solve(int64_t n, int64_t m,
     free(x); free(y); free(xa); free(ya); free(xt); free(yt); free(rhs); free(aty);
     free(xb); free(axb); free(dx); free(dy); free(dxr); free(dyr);
     free_problem(&pr);
+    if (info) info->seconds_total = wall_seconds() - t_call;
     return status;
 }

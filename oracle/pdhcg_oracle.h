@@ -72,6 +72,10 @@ typedef struct {
     double omega, eta, norm_A, norm_Q;
     double eps_inner;        /* final inner tolerance */
     double natural_residual; /* ||x - proj_X(x - r)||_inf at the returned point */
+    /* wall-clock seconds (instrumentation for the CPU baseline; no effect on
+     * any result): setup (norm estimates), the inner subproblem solves, the
+     * checks (KKT, certificates, restart), and the whole call */
+    double seconds_setup, seconds_inner, seconds_check, seconds_total;
 } oracle_info;
 
 void oracle_params_default(oracle_params* p);
@@ -158,6 +162,9 @@ int oracle_restart_test(double R, double R_start, double R_prev, int R_prev_vali
 double oracle_splitmix_unit(uint64_t i);
 
 int oracle_num_threads(void);
+/* Threads of the oracle's parallel loops from now on (n >= 1; results do not
+ * depend on it: reductions run in fixed chunks summed in chunk order). */
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
