@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdhcg_hip.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "batch.hip", "calib.hip", "host.cpp", "serve.cpp",
-                                                  "noalloc.cpp")]
+                                                  "noalloc.cpp", "prep.cpp")]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions anywhere (hipcc's host pass warns about

@@ -8,19 +8,9 @@
 #include <vector>
 
 #include "../../include/pdhcg.h"
+#include "prep.h"
 
 namespace pdhcg {
-
-extern thread_local std::string g_err;
-int fail(int code, const std::string& msg);
-double now_s();
-
-// input validation shared by every entry point that takes a problem
-int check_csr(const char* name, int64_t rows, int64_t cols, const int64_t* rp, const int32_t* cj,
-              const double* v);
-int check_symmetric(int64_t n, const int64_t* rp, const int32_t* cj, const double* v);
-int check_vec(const char* name, int64_t len, const double* v, bool allow_inf);
-int check_bounds(const char* name, int64_t len, const double* l, const double* u);
 
 // A region of device memory the library does not own (the static workspace of
 // qp_batch_solve_static): allocations are carved from it in 256-byte steps
