@@ -792,6 +792,10 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
 
     long long gseq = 1;
     int64_t k = 0;
+    // the round's step count t, tracked here for the closed-form path (the
+    // device resets it at a restart, which only a check decides; the host
+    // reads it back after every check)
+    long long t_round = 0;
     int status = QP_NOT_SOLVED;
     for (;;) {
         if (k > 0 || p.max_iter == 0) {
@@ -809,6 +813,8 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                     status = st;
                     break;
                 }
+                if (S.qdiag)
+                    HIPCHK(copy_wait(&t_round, &S.ctrl->t, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
             }
         }
         if (k >= p.max_iter) {
@@ -816,9 +822,13 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
             break;
         }
         const int next_check = ((k + 1) % p.check_every == 0) || (k + 1 >= p.max_iter);
+        // closed-form path: the movement norms are read only at the round's
+        // first step (the restart test's reference) and before a check, so
+        // the other iterations skip their reductions and finishing step
+        const bool reduce = !S.qdiag || next_check || t_round == 0;
         if (S.qdiag) {
             Timed t(h, QP_FAM_RHS);
-            HIPCHK(launch_prox_diag(S, next_check, s));
+            HIPCHK(launch_prox_diag(S, next_check, t_round, reduce, s));
         } else {
             // the gradient is formed with a product with Q at the first
             // iteration and after every check (bounds the drift of the
@@ -836,9 +846,11 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
         {
             Timed t(h, QP_FAM_DUAL);
             const int pre = S.qdiag ? (prox_diag_deferrable(S) ? PRE_PROX : PRE_NONE) : PRE_XBAR;
-            HIPCHK(launch_dual(S, next_check, pre, s));
+            if (S.qdiag) HIPCHK(launch_dual(S, next_check, pre, t_round, k, reduce, s));
+            else HIPCHK(launch_dual(S, next_check, pre, -1, -1, true, s));
         }
         ++k;
+        ++t_round;
     }
     HIPCHK(hipStreamSynchronize(s));
     const double t1 = now_s();

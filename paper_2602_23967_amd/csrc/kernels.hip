@@ -156,7 +156,7 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
     if (!f32) spmv_block<E, double>(M, e, M.val, prodbuf, srp, lds, acc);
 
     if constexpr (E::NR > 0) {
-        if (M.nparts > 1) return;   // the row pass reduces
+        if (M.nparts > 1 || !e.reduce) return;   // the row pass reduces, or nothing does
         block_reduce<E>(acc, lds);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -187,6 +187,7 @@ __global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
         e.row((int)i, s, acc);
     }
     if constexpr (E::NR > 0) {
+        if (!e.reduce) return;
         block_reduce<E>(acc, lds);
         if (threadIdx.x == 0) {
 #pragma unroll
@@ -277,9 +278,13 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
     E e = epi;
     if (e.skip()) return;
     e.init();
+    // e.reduce == 0: only the long rows are completed (no reductions, no
+    // finishing step, the control block untouched)
     if constexpr (E::NR > 0) {
-        ctrl_to_lds(e.ctrl, sctrl);
-        finish_pre(pre, pre_nblk, pre_partials, sctrl);
+        if (e.reduce) {
+            ctrl_to_lds(e.ctrl, sctrl);
+            finish_pre(pre, pre_nblk, pre_partials, sctrl);
+        }
     }
     double acc[NR];
 #pragma unroll
@@ -312,6 +317,7 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
         }
     }
     if constexpr (E::NR > 0) {
+        if (!e.reduce) return;
 #pragma unroll 4
         for (int b = threadIdx.x; b < M.nblk; b += FIN_T) {
 #pragma unroll
@@ -377,6 +383,10 @@ struct EpiBase {
     // run from the FP32 copy of the matrix when the solve is in mixed precision
     static constexpr bool BULK = false;
     Ctrl* ctrl;
+    // 0: nothing reads this launch's reductions (an iteration of the
+    // closed-form path between the round's first step and the step before a
+    // check), so its kernels leave no partials and no finishing step runs
+    int reduce = 1;
     __device__ bool skip() const { return false; }
     __device__ void init() {}
     // mixed precision (BULK epilogues): whether this launch takes the FP32
@@ -418,9 +428,10 @@ struct HalpernX {
     int store;
     double w, wa, th;
     int halpern, unb;
+    long long tk = -1;   // >= 0: the round's step count t, given by the host (else ctrl->t)
     __device__ void init(const Ctrl* ctrl)
     {
-        const double t = (double)ctrl->t;
+        const double t = (double)(tk >= 0 ? tk : ctrl->t);
         w = (t + 1.0) / (t + 2.0);
         wa = 1.0 / (t + 2.0);
         th = ctrl->theta;
@@ -785,11 +796,14 @@ struct EpiDual : EpiBase {
     __device__ double rowref(int i) const { return axref[i]; }
     double sigma, w, wa, th;
     int halpern;
+    // >= 0: the iteration count k and the round's step count t, given by the
+    // host (the closed-form path), else read from ctrl
+    long long tk = -1, kk = -1;
     __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
     __device__ void init()
     {
         sigma = ctrl->sigma;
-        const double t = (double)ctrl->t;
+        const double t = (double)(tk >= 0 ? tk : ctrl->t);
         w = (t + 1.0) / (t + 2.0);
         wa = 1.0 / (t + 2.0);
         th = ctrl->theta;
@@ -826,8 +840,13 @@ struct EpiDual : EpiBase {
             C->ptil_sum = t[2];
             C->ptil_abs = t[3];
         }
-        C->k += 1;
-        C->t += 1;
+        if (tk >= 0) {
+            C->k = kk + 1;
+            C->t = tk + 1;
+        } else {
+            C->k += 1;
+            C->t += 1;
+        }
         if (C->t == 1) C->R_start = sqrt(C->omega * C->ndx2 + C->ndy2 / C->omega);
     }
 };
@@ -1234,20 +1253,21 @@ static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipSt
                            const Pre& pre = Pre{}, int pre_nblk = 0)
 {
     double* part = defer ? S.partials2 : S.partials;
+    // e.reduce == 0: no finishing step, except the completion of long rows
+    const bool fin = e.reduce && E::NR > 0 && !defer;
     if (M.nparts > 1) {
         const int grid = vec_grid(M.rows);
         if (S.tev) (void)hipEventRecord(S.tev[0], s);
         launch_spmv_main(M, e, part, s);
         k_rows<E><<<grid, TPB, 0, s>>>(M, e, part);
         if (S.tev) (void)hipEventRecord(S.tev[1], s);
-        if (E::NR > 0 && !defer)
-            k_vec_fin<E, Pre><<<1, FIN_T, 0, s>>>(grid, e, part, pre, pre_nblk, S.partials2);
+        if (fin) k_vec_fin<E, Pre><<<1, FIN_T, 0, s>>>(grid, e, part, pre, pre_nblk, S.partials2);
         return hipGetLastError();
     }
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
     launch_spmv_main(M, e, part, s);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
-    if ((E::NR > 0 || M.nlr > 0) && !defer)
+    if (fin || (M.nlr > 0 && !defer))
         k_spmv_fin<E, Pre><<<1, FIN_T, 0, s>>>(M, e, part, pre, pre_nblk, S.partials2);
     return hipGetLastError();
 }
@@ -1299,9 +1319,12 @@ static EpiProx prox_epi(const DevState& S, int store_delta)
 // the product has no long rows to complete there.
 bool prox_diag_deferrable(const DevState& S) { return S.AT.nlr == 0; }
 
-hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s)
+hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, hipStream_t s)
 {
-    return run_spmv(S, S.AT, prox_epi(S, store_delta), s, prox_diag_deferrable(S));
+    EpiProx e = prox_epi(S, store_delta);
+    e.hx.tk = tk;
+    e.reduce = reduce ? 1 : 0;
+    return run_spmv(S, S.AT, e, s, prox_diag_deferrable(S));
 }
 
 hipError_t launch_rhs(const DevState& S, hipStream_t s)
@@ -1410,15 +1433,22 @@ hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_dual(const DevState& S, int store_delta, int pre, hipStream_t s)
+hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk, long long kk, bool reduce,
+                       hipStream_t s)
 {
     EpiDual e{};
     e.ctrl = S.ctrl;
     e.xbar = S.xbar; e.ya = S.ya; e.lc = S.lc; e.uc = S.uc;
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
+    e.tk = tk;
+    e.kk = kk;
+    e.reduce = reduce ? 1 : 0;
     if (S.mixed) { e.dxb32 = S.dxb32; e.axref = S.axref; e.yref = S.yref; e.dy32 = S.dy32; }
-    if (pre == PRE_PROX)
-        return run_spmv(S, S.A, e, s, false, prox_epi(S, store_delta), spmv_partial_blocks(S.AT));
+    if (pre == PRE_PROX) {
+        EpiProx pe = prox_epi(S, store_delta);
+        pe.hx.tk = tk;
+        return run_spmv(S, S.A, e, s, false, pe, spmv_partial_blocks(S.AT));
+    }
     if (pre == PRE_XBAR)
         return run_spmv(S, S.A, e, s, false, xbar_epi(S, store_delta), vec_grid(S.n));
     return run_spmv(S, S.A, e, s);

@@ -129,7 +129,10 @@ hipError_t launch_init_start(const DevState& S, hipStream_t s);
 // closed-form primal step fused with x_bar and the Halpern average of x
 // the closed-form primal step; its finishing work is left for the dual
 // step's finishing kernel when prox_diag_deferrable(S)
-hipError_t launch_prox_diag(const DevState& S, int store_delta, hipStream_t s);
+// tk: the round's step count t from the host (>= 0) or -1 (read ctrl->t);
+// reduce = false: nothing reads this iteration's reductions (no partials,
+// and the dual step's finishing kernel only completes long rows)
+hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, hipStream_t s);
 bool prox_diag_deferrable(const DevState& S);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
@@ -149,7 +152,9 @@ hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- pro
 // dual step and Halpern on y; pre names the earlier epilogue whose finishing
 // work its finishing kernel runs first (same store_delta)
 enum { PRE_NONE = 0, PRE_PROX = 1, PRE_XBAR = 2 };
-hipError_t launch_dual(const DevState& S, int store_delta, int pre, hipStream_t s);
+// tk, kk: t and the iteration count k from the host (>= 0) or -1 (ctrl)
+hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk, long long kk, bool reduce,
+                       hipStream_t s);
 // KKT pieces at (x, y); with `full` also the infeasibility certificates
 // (and, with `dinf`, the unboundedness ones) and the solver's decision
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,
