@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QPs solved/s at 1e-6 rel KKT + achieved HBM GB/s; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+SERVE_VERIFY_SEED = 2602_23967
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_hp_large_sparse.json")
 
 
@@ -473,6 +474,7 @@ def main_serve(args, torch, P, I):
             s1.solve(p64)
         one += time.perf_counter() - a
         n_one += 1
+    verify = None if args.no_cpu_baseline else verify_served(qs, res, args, P)
     out = {
         "metric": METRIC,
         "value": int(np.sum(ok)) / (last - first),
@@ -491,8 +493,53 @@ def main_serve(args, torch, P, I):
         "roofline": None,
         "one_at_a_time": {"value": n_one / one if one else None, "unit": "QPs solved/s",
                           "sample": f"first {n_one} requests of the stream, qp_create + qp_solve each, FP64"},
+        "oracle_verified": verify,
     }
     print(json.dumps(out), flush=True)
+
+
+def verify_served(qs, res, args, P):
+    """The served results against the CPU oracle: a seeded 5 % sample of the
+    requests plus every infeasible one, smallest first, within
+    --verify-budget-s of oracle time.  A result is verified when its status
+    is the oracle's and, if OPTIMAL, the oracle's KKT evaluation of the
+    returned point is <= tol and the objective is within 1e-6 (1 + |f|) of
+    the oracle's (solved at tol 1e-9, or 1e-7 above 20,000 variables)."""
+    import oracle
+    rng = np.random.default_rng(SERVE_VERIFY_SEED)
+    pick = set(int(i) for i in rng.choice(len(qs), size=max(1, int(round(0.05 * len(qs)))), replace=False))
+    pick |= {i for i, q in enumerate(qs) if q.name.endswith("_infeasible")}
+    order = sorted(pick, key=lambda i: qs[i].n + qs[i].m)
+    t0 = time.perf_counter()
+    rows, by_kind = [], {}
+    for i in order:
+        if time.perf_counter() - t0 > args.verify_budget_s:
+            break
+        q, (g, _) = qs[i], res[i]
+        ref_tol = 1e-9 if q.n <= 20000 else 1e-7
+        o = oracle.solve(q, tol=ref_tol, max_iter=1_000_000)
+        good = g.status == o.status
+        kkt = ferr = None
+        if good and o.status == P.OPTIMAL:
+            k = oracle.kkt(q, g.x, g.y)
+            kkt = max(k["r_primal"], k["r_dual"], k["r_gap"])
+            ferr = abs(g.info["primal_obj"] - o.info["primal_obj"]) / (1 + abs(o.info["primal_obj"]))
+            good = kkt <= args.tol and ferr <= 1e-6
+        kind = q.name.split("_")[0].rstrip("0123456789")
+        b = by_kind.setdefault(kind, [0, 0])
+        b[0] += 1
+        b[1] += int(good)
+        rows.append({"request": i, "name": q.name, "n": q.n, "status": P.STATUS_NAMES[g.status],
+                     "oracle_status": oracle.STATUS_NAMES[o.status], "kkt": kkt, "objective_rel_err": ferr,
+                     "verified": bool(good)})
+        log(f"verify request {i} ({q.name}): {rows[-1]['status']} vs oracle {rows[-1]['oracle_status']}, "
+            f"kkt {kkt}, objective error {ferr}: {'ok' if good else 'MISMATCH'}")
+    return {"selected": len(order), "checked": len(rows), "verified": sum(r["verified"] for r in rows),
+            "by_kind": {k: {"checked": v[0], "verified": v[1]} for k, v in by_kind.items()},
+            "oracle_seconds": time.perf_counter() - t0, "cores": oracle.num_threads(),
+            "sample": f"seeded 5% of {len(qs)} requests (seed {SERVE_VERIFY_SEED}) plus every infeasible request, "
+                      f"smallest first, {args.verify_budget_s:g}s oracle budget",
+            "mismatches": [r for r in rows if not r["verified"]]}
 
 
 def main():
@@ -541,6 +588,8 @@ def main():
                     help="also time the oracle's whole solve (child process, --cpu-budget-s)")
     ap.add_argument("--cpu-budget-s", type=float, default=900.0)
     ap.add_argument("--oracle-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--verify-budget-s", type=float, default=90.0,
+                    help="oracle time for verifying the served stream's sample")
     args = ap.parse_args()
 
     if args.oracle_child:
