@@ -541,7 +541,7 @@ int ensure_inner_graph(qp_handle* h, int K)
     return 0;
 }
 
-int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact, int K)
+int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact, int K, bool pre_xbar = false)
 {
     DevState& S = h->S;
     hipStream_t s = h->stream;
@@ -551,7 +551,7 @@ int inner_solve(qp_handle* h, long long& gseq, int lag, bool exact, int K)
         HIPCHK(launch_ginit(S, base, s));
     } else {
         Timed t(h, QP_FAM_RHS);
-        HIPCHK(launch_rhs_grad(S, base, s));
+        HIPCHK(launch_rhs_grad(S, base, pre_xbar, s));
     }
     volatile unsigned long long* word = h->hstat;
     long long issued = 0;
@@ -796,6 +796,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     // device resets it at a restart, which only a check decides; the host
     // reads it back after every check)
     long long t_round = 0;
+    bool xbar_pending = false;   // the last x_bar kernel's finishing work is still to run
     int status = QP_NOT_SOLVED;
     for (;;) {
         if (k > 0 || p.max_iter == 0) {
@@ -813,8 +814,7 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                     status = st;
                     break;
                 }
-                if (S.qdiag)
-                    HIPCHK(copy_wait(&t_round, &S.ctrl->t, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(copy_wait(&t_round, &S.ctrl->t, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
             }
         }
         if (k >= p.max_iter) {
@@ -822,10 +822,13 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
             break;
         }
         const int next_check = ((k + 1) % p.check_every == 0) || (k + 1 >= p.max_iter);
-        // closed-form path: the movement norms are read only at the round's
-        // first step (the restart test's reference) and before a check, so
-        // the other iterations skip their reductions and finishing step
-        const bool reduce = !S.qdiag || next_check || t_round == 0;
+        // the movement norms and certificate pieces are read only at the
+        // round's first step (the restart test's reference) and before a
+        // check: the other iterations skip the dual step's reductions and
+        // finishing step (a non-diagonal Q's x_bar finishing work, which
+        // updates the inner tolerance, then rides with the next iteration's
+        // right-hand side instead)
+        const bool reduce = next_check || t_round == 0;
         if (S.qdiag) {
             Timed t(h, QP_FAM_RHS);
             HIPCHK(launch_prox_diag(S, next_check, t_round, reduce, s));
@@ -838,16 +841,16 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
                 Timed t(h, QP_FAM_RHS);
                 HIPCHK(launch_rhs(S, s));
             }
-            int rc = inner_solve(h, gseq, p.inner_lag, exact, K);
+            int rc = inner_solve(h, gseq, p.inner_lag, exact, K, xbar_pending);
             if (rc) return rc;
             Timed t(h, QP_FAM_HALPX);
-            HIPCHK(launch_xbar(S, next_check, s));
+            HIPCHK(launch_xbar(S, next_check, t_round, s));
         }
         {
             Timed t(h, QP_FAM_DUAL);
             const int pre = S.qdiag ? (prox_diag_deferrable(S) ? PRE_PROX : PRE_NONE) : PRE_XBAR;
-            if (S.qdiag) HIPCHK(launch_dual(S, next_check, pre, t_round, k, reduce, s));
-            else HIPCHK(launch_dual(S, next_check, pre, -1, -1, true, s));
+            HIPCHK(launch_dual(S, next_check, pre, t_round, k, reduce, s));
+            xbar_pending = !S.qdiag && !reduce;
         }
         ++k;
         ++t_round;

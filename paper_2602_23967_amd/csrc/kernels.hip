@@ -179,6 +179,7 @@ __global__ __launch_bounds__(TPB) void k_rows(CsrDev M, E epi, double* partials)
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
     const long long stride = (long long)gridDim.x * TPB;
+#pragma unroll 2
     for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < M.rows; i += stride) {
         double s = 0.0;
 #pragma unroll
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(TPB) void k_vec(long long len, E epi, double* parti
 #pragma unroll
     for (int j = 0; j < NR; ++j) acc[j] = rid(E::kind(j));
     const long long stride = (long long)gridDim.x * TPB;
+#pragma unroll 2
     for (long long i = (long long)blockIdx.x * TPB + threadIdx.x; i < len; i += stride) e.elem(i, acc);
     if constexpr (E::NR > 0) {
         block_reduce<E>(acc, lds);
@@ -640,12 +642,16 @@ struct EpiGinit : EpiBase {
 
 // inner step, part A: H p = Q p + p/tau with p'Hp, g'p and the feasible
 // step; or, right after an expansion step, the fresh gradient g = H x - rhs
+template <int BM>   // BoundVec storage mode of the box
 struct EpiStepA : EpiBase {
     static constexpr bool BULK = true;
     static constexpr int NR = 4;
-    const double *p, *rhs;
+    const double* __restrict__ p;
+    const double* __restrict__ rhs;
     BoundVec lv, uv;
-    double *xt, *g, *hp;
+    double* __restrict__ xt;
+    double* __restrict__ g;
+    double* __restrict__ hp;
     unsigned long long* dstat;
     double it, abar;
     int ng;
@@ -658,23 +664,25 @@ struct EpiStepA : EpiBase {
     __device__ double xval(int j) const { return ng ? xt[j] : p[j]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
+        const double l = lv.template at<BM>(i), u = uv.template at<BM>(i);
         if (ng) {
-            const double xi = xt[i];
-            const double gi = s + it * xi - rhs[i];
+            const double xi = xt[i], ri = rhs[i];
+            const double gi = s + it * xi - ri;
             g[i] = gi;
-            const Split sp = split(xi, gi, lv[i], uv[i], abar);
+            const Split sp = split(xi, gi, l, u, abar);
             a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
             a[1] += sp.beta * sp.beta;
             a[2] += sp.phit * sp.phi;
         } else {
-            const double pi = p[i], xi = xt[i];
+            // every load first, then the arithmetic and the store
+            const double pi = p[i], xi = xt[i], gi = g[i];
             const double h = s + it * pi;
             hp[i] = h;
             a[0] += pi * h;
-            a[1] += g[i] * pi;
+            a[1] += gi * pi;
             double st = INFINITY;
-            if (pi > 0.0 && isfinite(lv[i])) st = (xi - lv[i]) / pi;
-            else if (pi < 0.0 && isfinite(uv[i])) st = (xi - uv[i]) / pi;
+            if (pi > 0.0 && isfinite(l)) st = (xi - l) / pi;
+            else if (pi < 0.0 && isfinite(u)) st = (xi - u) / pi;
             a[3] = fmin(a[3], st);
         }
     }
@@ -716,11 +724,14 @@ struct EpiStepA : EpiBase {
 
 // inner step, part B: x <- clip(x - alpha p), g <- g - alpha Hp; expansion
 // adds the projected step x <- clip(x - abar phi(x)) and asks for a fresh g
+template <int BM>
 struct EpiStepB : EpiBase {
     static constexpr int NR = 4;
-    const double *p, *hp;
+    const double* __restrict__ p;
+    const double* __restrict__ hp;
     BoundVec lv, uv;
-    double *xt, *g;
+    double* __restrict__ xt;
+    double* __restrict__ g;
     unsigned long long* dstat;
     double alpha, abar;
     int kindstep;
@@ -728,9 +739,10 @@ struct EpiStepB : EpiBase {
     __device__ void init() { alpha = ctrl->alpha; abar = ctrl->abar; kindstep = ctrl->step_kind; }
     __device__ void elem(long long i, Acc<NR> a) const
     {
-        const double l = lv[i], u = uv[i];
-        double xi = clampd(xt[i] - alpha * p[i], l, u);
-        const double gi = g[i] - alpha * hp[i];
+        const double l = lv.template at<BM>(i), u = uv.template at<BM>(i);
+        const double x0 = xt[i], pi = p[i], g0 = g[i], hi = hp[i];
+        double xi = clampd(x0 - alpha * pi, l, u);
+        const double gi = g0 - alpha * hi;
         g[i] = gi;
         const Split sp = split(xi, gi, l, u, abar);
         if (kindstep == STEP_EXPAND) {
@@ -739,7 +751,7 @@ struct EpiStepB : EpiBase {
             a[0] += sp.phi * sp.phi + sp.beta * sp.beta;
             a[1] += sp.beta * sp.beta;
             a[2] += sp.phit * sp.phi;
-            a[3] += sp.phi * hp[i];
+            a[3] += sp.phi * hi;
         }
         xt[i] = xi;
     }
@@ -762,19 +774,22 @@ struct EpiStepB : EpiBase {
 };
 
 // next direction: beta (proportioning), phi, or phi - gam p (conjugate)
+template <int BM>
 struct EpiDir : EpiBase {
     static constexpr int NR = 0;
-    const double *xt, *g;
+    const double* __restrict__ xt;
+    const double* __restrict__ g;
     BoundVec lv, uv;
-    double* p;
+    double* __restrict__ p;
     double gam, abar;
     int mode;
     __device__ bool skip() const { return ctrl->done != 0 || ctrl->need_g != 0; }
     __device__ void init() { gam = ctrl->gam; abar = ctrl->abar; mode = ctrl->dir_mode; }
     __device__ void elem(long long i, Acc<NR>) const
     {
-        const Split sp = split(xt[i], g[i], lv[i], uv[i], abar);
-        p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * p[i]);
+        const double pi = p[i];
+        const Split sp = split(xt[i], g[i], lv.template at<BM>(i), uv.template at<BM>(i), abar);
+        p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * pi);
     }
 };
 
@@ -1336,13 +1351,18 @@ hipError_t launch_rhs(const DevState& S, hipStream_t s)
     return run_spmv(S, S.AT, e, s);
 }
 
-hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s)
+static EpiXbar xbar_epi(const DevState& S, int store_delta);
+
+hipError_t launch_rhs_grad(const DevState& S, long long seq, bool pre_xbar, hipStream_t s)
 {
     EpiRhsGrad e{};
     e.ctrl = S.ctrl;
     e.y = S.y; e.x = S.x; e.c = S.c; e.xt = S.xt; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.g = S.g;
     e.dstat = S.dstat; e.seq = seq;
     if (S.mixed) { e.dy32 = S.dy32; e.atyref = S.atyref; }
+    // the previous iteration's x_bar / Halpern finishing work (its inner
+    // tolerance update first: this kernel's decision reads it)
+    if (pre_xbar) return run_spmv(S, S.AT, e, s, false, xbar_epi(S, 0), vec_grid(S.n));
     return run_spmv(S, S.AT, e, s);
 }
 
@@ -1374,12 +1394,44 @@ hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s)
     return run_spmv(S, S.Q, e, s);
 }
 
-hipError_t launch_dir(const DevState& S, hipStream_t s)
+// The inner step's kernels are compiled per storage mode of the box (one
+// pair, byte classes, arrays; BoundVec): the host picks the instance.
+template <int BM>
+static hipError_t launch_dir_m(const DevState& S, hipStream_t s)
 {
-    EpiDir e{};
+    EpiDir<BM> e{};
     e.ctrl = S.ctrl;
     e.xt = S.xt; e.g = S.g; e.lv = S.lv; e.uv = S.uv; e.p = S.p;
     return run_vec(S, S.n, e, s);
+}
+
+template <int BM>
+static hipError_t launch_hp_m(const DevState& S, hipStream_t s)
+{
+    EpiStepA<BM> e{};
+    e.ctrl = S.ctrl;
+    e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
+    e.dstat = S.dstat; e.mixed = S.mixed;
+    return run_spmv(S, S.Q, e, s);
+}
+
+template <int BM>
+static hipError_t launch_update_m(const DevState& S, hipStream_t s)
+{
+    EpiStepB<BM> e{};
+    e.ctrl = S.ctrl;
+    e.p = S.p; e.hp = S.hp; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt; e.g = S.g;
+    e.dstat = S.dstat;
+    return run_vec(S, S.n, e, s);
+}
+
+hipError_t launch_dir(const DevState& S, hipStream_t s)
+{
+    switch (S.lv.mode) {
+    case 1: return launch_dir_m<1>(S, s);
+    case 2: return launch_dir_m<2>(S, s);
+    default: return launch_dir_m<0>(S, s);
+    }
 }
 
 hipError_t launch_hp(const DevState& S, hipStream_t s)
@@ -1391,20 +1443,20 @@ hipError_t launch_hp(const DevState& S, hipStream_t s)
         hipError_t err = run_spmv(S, S.R, t, s);
         if (err != hipSuccess) return err;
     }
-    EpiStepA e{};
-    e.ctrl = S.ctrl;
-    e.p = S.p; e.lv = S.lv; e.uv = S.uv; e.rhs = S.rhs; e.xt = S.xt; e.g = S.g; e.hp = S.hp;
-    e.dstat = S.dstat; e.mixed = S.mixed;
-    return run_spmv(S, S.Q, e, s);
+    switch (S.lv.mode) {
+    case 1: return launch_hp_m<1>(S, s);
+    case 2: return launch_hp_m<2>(S, s);
+    default: return launch_hp_m<0>(S, s);
+    }
 }
 
 hipError_t launch_update(const DevState& S, hipStream_t s)
 {
-    EpiStepB e{};
-    e.ctrl = S.ctrl;
-    e.p = S.p; e.hp = S.hp; e.lv = S.lv; e.uv = S.uv; e.xt = S.xt; e.g = S.g;
-    e.dstat = S.dstat;
-    return run_vec(S, S.n, e, s);
+    switch (S.lv.mode) {
+    case 1: return launch_update_m<1>(S, s);
+    case 2: return launch_update_m<2>(S, s);
+    default: return launch_update_m<0>(S, s);
+    }
 }
 
 static EpiXbar xbar_epi(const DevState& S, int store_delta)
@@ -1420,9 +1472,11 @@ static EpiXbar xbar_epi(const DevState& S, int store_delta)
 // x_bar and the Halpern average of x after an inner solve; its finishing
 // work is carried into the dual step's finishing kernel (as for the
 // closed-form primal step)
-hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s)
+hipError_t launch_xbar(const DevState& S, int store_delta, long long tk, hipStream_t s)
 {
-    return run_vec(S, S.n, xbar_epi(S, store_delta), s, true);
+    EpiXbar e = xbar_epi(S, store_delta);
+    e.hx.tk = tk;
+    return run_vec(S, S.n, e, s, true);
 }
 
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
@@ -1449,8 +1503,11 @@ hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk
         pe.hx.tk = tk;
         return run_spmv(S, S.A, e, s, false, pe, spmv_partial_blocks(S.AT));
     }
-    if (pre == PRE_XBAR)
-        return run_spmv(S, S.A, e, s, false, xbar_epi(S, store_delta), vec_grid(S.n));
+    if (pre == PRE_XBAR) {
+        EpiXbar xe = xbar_epi(S, store_delta);
+        xe.hx.tk = tk;
+        return run_spmv(S, S.A, e, s, false, xe, vec_grid(S.n));
+    }
     return run_spmv(S, S.A, e, s);
 }
 

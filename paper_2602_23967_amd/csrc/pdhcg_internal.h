@@ -91,6 +91,15 @@ struct BoundVec {
     {
         return mode == 1 ? k : (mode == 2 ? tab[cls[i]] : a[i]);
     }
+    // the same value with the storage mode known at compile time (the
+    // inner step's kernels are compiled per mode: no branch per entry)
+    template <int M>
+    __device__ __forceinline__ double at(long long i) const
+    {
+        if constexpr (M == 1) return k;
+        else if constexpr (M == 2) return tab[cls[i]];
+        else return a[i];
+    }
 };
 
 struct DevState {
@@ -140,14 +149,16 @@ hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
 hipError_t launch_tail(const DevState& S, const double* v, double* tail, bool bulk, hipStream_t s);
 // rhs and warm-start gradient of the next subproblem from the previous one's
 // gradient (no product with Q); starts the inner solve like launch_ginit
-hipError_t launch_rhs_grad(const DevState& S, long long seq, hipStream_t s);
+// pre_xbar: the previous iteration's x_bar kernel left its finishing work
+// (the dual step ran without one)
+hipError_t launch_rhs_grad(const DevState& S, long long seq, bool pre_xbar, hipStream_t s);
 hipError_t launch_dir(const DevState& S, hipStream_t s);
 hipError_t launch_hp(const DevState& S, hipStream_t s);
 hipError_t launch_update(const DevState& S, hipStream_t s);
 // x_bar = 2 x_T - x fused with the Halpern average of x
 // x_bar and Halpern on x; its finishing work is always left for the dual
 // step's finishing kernel (launch_dual with PRE_XBAR)
-hipError_t launch_xbar(const DevState& S, int store_delta, hipStream_t s);
+hipError_t launch_xbar(const DevState& S, int store_delta, long long tk, hipStream_t s);
 hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- proj_X(x)
 // dual step and Halpern on y; pre names the earlier epilogue whose finishing
 // work its finishing kernel runs first (same store_delta)
