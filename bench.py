@@ -310,7 +310,7 @@ def main_batch(args, torch, P, I):
                                                  "sample": f"the first {ns1} instances ({el1:.1f}s)"}}
     if args.cpu_full:
         out["cpu_full_solve"] = cpu_full("mpc_batch", args.tol, args.cpu_budget_s)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def portfolio_bytes(q, fam, vb):
@@ -406,7 +406,7 @@ def main_portfolio(args, torch, P, I):
         out["cpu_baseline"] = cpu_baseline(q, infos[-1], args.cpu_sample_iters or 4096, args.tol)
     if args.cpu_full:
         out["cpu_full_solve"] = cpu_full("portfolio", args.tol, args.cpu_budget_s)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main_serve(args, torch, P, I):
@@ -495,7 +495,7 @@ def main_serve(args, torch, P, I):
                           "sample": f"first {n_one} requests of the stream, qp_create + qp_solve each, FP64"},
         "oracle_verified": verify,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def verify_served(qs, res, args, P):
@@ -588,6 +588,8 @@ def main():
                     help="also time the oracle's whole solve (child process, --cpu-budget-s)")
     ap.add_argument("--cpu-budget-s", type=float, default=900.0)
     ap.add_argument("--oracle-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="default workload only: skip the other workloads' figures")
     ap.add_argument("--verify-budget-s", type=float, default=90.0,
                     help="oracle time for verifying the served stream's sample")
     args = ap.parse_args()
@@ -622,16 +624,27 @@ def main():
     if args.workload == "mpc_batch":
         if args.precision is None:
             args.precision = "mixed"
-        return main_batch(args, torch, P, I)
+        print(json.dumps(main_batch(args, torch, P, I)), flush=True)
+        return
     if args.workload == "portfolio":
         if args.precision is None:
             args.precision = "mixed"
-        return main_portfolio(args, torch, P, I)
+        print(json.dumps(main_portfolio(args, torch, P, I)), flush=True)
+        return
     if args.workload == "serve":
         if args.precision is None:
             args.precision = "mixed"
-        return main_serve(args, torch, P, I)
+        out = main_serve(args, torch, P, I)
+    else:
+        out = main_single(args, torch, P, I)
+        if args.workload == "large_sparse" and not args.no_secondary:
+            out["secondary"] = run_secondary(args, torch, P, I)
+    print(json.dumps(out), flush=True)
 
+
+def main_single(args, torch, P, I):
+    """One problem through qp_create / qp_solve: the n = 1e6 QP (default)
+    or the n = 1000 QP (--workload small)."""
     t = time.perf_counter()
     small = args.workload == "small"
     q = I.random_small(0) if small else I.large_sparse(0, n=args.n)
@@ -750,7 +763,38 @@ def main():
     if args.cpu_full and not small:
         out["cpu_full_solve"] = cpu_full("large_sparse", args.tol, args.cpu_budget_s)
         log(f"oracle full solve: {out['cpu_full_solve']}")
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def summary(out):
+    """The figures of a workload's line that the default run attaches for
+    the other workloads (measured in the same run)."""
+    keep = ("value", "unit", "ms_per_step", "steps", "dtype", "solved", "solved_count", "iterations",
+            "latency_s", "latency_us", "fp64_plain", "one_at_a_time", "error_vs_fp64")
+    d = {k: out[k] for k in keep if k in out}
+    d["workload"] = out["config"]["workload"]
+    r = out.get("roofline")
+    if r:
+        d["roofline"] = {k: r.get(k) for k in ("bound", "achieved", "peak", "unit", "frac", "kernel", "avg_us")}
+    return d
+
+
+def run_secondary(args, torch, P, I):
+    """The other workloads' lines in the default run: the factor portfolio
+    (mixed precision, with its FP64 solve), the 4096-instance MPC batch
+    (mixed, autotuned) and the n = 1000 QP (FP64, launch-bound), each timed
+    as its own --workload run would be, without CPU baselines."""
+    import copy
+    res = {}
+    for wl, prec, steps in (("portfolio", "mixed", 3), ("mpc_batch", "mixed", 3), ("small", None, 5)):
+        a = copy.copy(args)
+        a.workload, a.precision, a.steps, a.warmup = wl, prec, steps, 1
+        a.no_cpu_baseline, a.cpu_full = True, False
+        t = time.perf_counter()
+        out = {"portfolio": main_portfolio, "mpc_batch": main_batch, "small": main_single}[wl](a, torch, P, I)
+        res[wl] = summary(out)
+        log(f"secondary {wl}: {res[wl]['value']:.4g} {res[wl]['unit']} ({time.perf_counter() - t:.0f}s)")
+    return res
 
 
 if __name__ == "__main__":
