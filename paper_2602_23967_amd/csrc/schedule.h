@@ -16,7 +16,10 @@ constexpr int TPB = 256;        // threads per block for every kernel
 #endif
 constexpr int NNZ_CAP = PDHCG_NNZ_CAP;   // nonzeros staged in LDS per row block
 constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at most)
-constexpr int VEC_GRID_MAX = 2048;
+// blocks of an elementwise pass at most: 4 per CU; each thread then takes
+// several elements (1024 measured 1.3 % faster on the n = 1e6 QP than 2048,
+// and 0.3 % faster than 512; the other workloads do not change)
+constexpr int VEC_GRID_MAX = 1024;
 // XCD-aware column partitioning: an operand larger than PART_MIN_COLS
 // doubles is split into NPARTS contiguous column parts; block b of the
 // product works on part b % NPARTS, which on gfx950's round-robin dispatch of
