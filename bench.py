@@ -39,7 +39,7 @@ def log(msg):
 
 def kernels_digest():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "pdhcg_internal.h"):
+    for f in ("kernels.hip", "pdhcg_internal.h", "schedule.h"):
         with open(os.path.join(ROOT, "paper_2602_23967_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
