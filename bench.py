@@ -542,7 +542,7 @@ def verify_served(qs, res, args, P):
             "mismatches": [r for r in rows if not r["verified"]]}
 
 
-def main():
+def parser():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -592,7 +592,11 @@ def main():
                     help="default workload only: skip the other workloads' figures")
     ap.add_argument("--verify-budget-s", type=float, default=90.0,
                     help="oracle time for verifying the served stream's sample")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = parser().parse_args()
 
     if args.oracle_child:
         return oracle_child(args.oracle_child, args.tol)
@@ -769,8 +773,8 @@ def main_single(args, torch, P, I):
 def summary(out):
     """The figures of a workload's line that the default run attaches for
     the other workloads (measured in the same run)."""
-    keep = ("value", "unit", "ms_per_step", "steps", "dtype", "solved", "solved_count", "iterations",
-            "latency_s", "latency_us", "fp64_plain", "one_at_a_time", "error_vs_fp64")
+    keep = ("value", "unit", "ms_per_step", "steps", "dtype", "solved", "solved_count", "requests", "iterations",
+            "latency_s", "latency_us", "fp64_plain", "one_at_a_time", "error_vs_fp64", "oracle_verified")
     d = {k: out[k] for k in keep if k in out}
     d["workload"] = out["config"]["workload"]
     r = out.get("roofline")
@@ -782,16 +786,25 @@ def summary(out):
 def run_secondary(args, torch, P, I):
     """The other workloads' lines in the default run: the factor portfolio
     (mixed precision, with its FP64 solve), the 4096-instance MPC batch
-    (mixed, autotuned) and the n = 1000 QP (FP64, launch-bound), each timed
-    as its own --workload run would be, without CPU baselines."""
+    (mixed, autotuned), the n = 1000 QP (FP64, launch-bound) and the served
+    stream (mixed), each timed as its own --workload run would be, without
+    CPU baselines; the served stream keeps its oracle check of a sample
+    (unless --no-cpu-baseline) with shorter budgets for that check and for
+    its one-at-a-time comparison."""
     import copy
     res = {}
-    for wl, prec, steps in (("portfolio", "mixed", 3), ("mpc_batch", "mixed", 3), ("small", None, 5)):
+    runs = {"portfolio": main_portfolio, "mpc_batch": main_batch, "small": main_single, "serve": main_serve}
+    for wl, prec, steps in (("portfolio", "mixed", 3), ("mpc_batch", "mixed", 3), ("small", None, 5),
+                            ("serve", "mixed", 1)):
         a = copy.copy(args)
         a.workload, a.precision, a.steps, a.warmup = wl, prec, steps, 1
         a.no_cpu_baseline, a.cpu_full = True, False
+        if wl == "serve":
+            a.no_cpu_baseline = args.no_cpu_baseline
+            a.verify_budget_s = min(args.verify_budget_s, 45.0)
+            a.one_at_a_time_s = min(args.one_at_a_time_s, 15.0)
         t = time.perf_counter()
-        out = {"portfolio": main_portfolio, "mpc_batch": main_batch, "small": main_single}[wl](a, torch, P, I)
+        out = runs[wl](a, torch, P, I)
         res[wl] = summary(out)
         log(f"secondary {wl}: {res[wl]['value']:.4g} {res[wl]['unit']} ({time.perf_counter() - t:.0f}s)")
     return res

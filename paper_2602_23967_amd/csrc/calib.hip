@@ -52,17 +52,25 @@ extern "C" int qp_measure_gather_rate(int64_t n, int64_t gathers, int32_t repeat
     const long long blocks = (gathers + CAL_T * CAL_PER - 1) / (CAL_T * CAL_PER);
     if (blocks > (1ll << 22)) return fail(QP_ERR_INVALID_ARG, "too many gathers");   // thread ids fit 32 bits
     const long long part_len = n / NPARTS;
+    // a stream of its own, never the legacy null stream: once the null
+    // stream has run kernels, a request server created later in the same
+    // process measured its batched launches up to 5x slower beside its
+    // single-problem workers
     double *x = nullptr, *out = nullptr;
+    hipStream_t s = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto cleanup = [&]() {
+        if (s) (void)hipStreamSynchronize(s);
         if (x) (void)hipFree(x);
         if (out) (void)hipFree(out);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (s) (void)hipStreamDestroy(s);
     };
-    hipError_t e = hipMalloc(&x, sizeof(double) * (size_t)n);
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&x, sizeof(double) * (size_t)n);
     if (e == hipSuccess) e = hipMalloc(&out, sizeof(double) * (size_t)blocks * CAL_T);
-    if (e == hipSuccess) e = hipMemset(x, 0, sizeof(double) * (size_t)n);
+    if (e == hipSuccess) e = hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s);
     if (e == hipSuccess) e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
     if (e != hipSuccess) {
@@ -71,15 +79,15 @@ extern "C" int qp_measure_gather_rate(int64_t n, int64_t gathers, int32_t repeat
     }
     float ms = 0.0f;
     for (int w = 0; w < 3 && e == hipSuccess; ++w) {
-        k_gather_calib<<<(unsigned)blocks, CAL_T>>>(x, part_len, NPARTS, out);
+        k_gather_calib<<<(unsigned)blocks, CAL_T, 0, s>>>(x, part_len, NPARTS, out);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[0], nullptr);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
     for (int r = 0; r < repeats && e == hipSuccess; ++r) {
-        k_gather_calib<<<(unsigned)blocks, CAL_T>>>(x, part_len, NPARTS, out);
+        k_gather_calib<<<(unsigned)blocks, CAL_T, 0, s>>>(x, part_len, NPARTS, out);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[1], nullptr);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
     cleanup();

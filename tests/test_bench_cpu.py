@@ -55,3 +55,55 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _served_results(qs):
+    """Stand-ins for the server's results: the oracle's own solutions (the
+    check below must accept them)."""
+    import types
+    import oracle
+    res = []
+    for q in qs:
+        o = oracle.solve(q, tol=1e-9, max_iter=1_000_000)
+        g = types.SimpleNamespace(status=o.status, x=o.x.copy(), y=o.y.copy(),
+                                  info={"primal_obj": o.info["primal_obj"]})
+        res.append((g, {}))
+    return res
+
+
+def test_verify_served_accepts_and_flags():
+    """The served stream's oracle check: a seeded 5 % sample plus every
+    infeasible request; agreeing results verify, a planted objective error
+    or a wrong status is reported as a mismatch."""
+    import types
+    import paper_2602_23967_amd as P
+    qs = [I.tiny(i) for i in range(19)] + [I.random_small(7, n=200, infeasible=True)]
+    args = types.SimpleNamespace(verify_budget_s=120.0, tol=1e-6)
+    res = _served_results(qs)
+    v = bench.verify_served(qs, res, args, P)
+    assert v["selected"] == 2 and v["checked"] == 2 and v["verified"] == 2, v
+    assert v["mismatches"] == []
+    assert res[19][0].status == P.PRIMAL_INFEASIBLE
+    # the sampled request (the one that is not the infeasible one)
+    rng = np.random.default_rng(bench.SERVE_VERIFY_SEED)
+    picked = int(rng.choice(len(qs), size=1, replace=False)[0])
+    assert picked != 19
+    g = res[picked][0]
+    assert g.status == P.OPTIMAL
+    g.info["primal_obj"] += 1e-3 * (1 + abs(g.info["primal_obj"]))
+    res[19][0].status = P.OPTIMAL
+    v = bench.verify_served(qs, res, args, P)
+    assert v["verified"] == 0 and len(v["mismatches"]) == 2
+    assert {r["request"] for r in v["mismatches"]} == {picked, 19}
+
+
+def test_summary_keeps_served_figures():
+    out = {"value": 5.0, "unit": "QPs solved/s", "ms_per_step": 1.0, "steps": 1, "dtype": "f64",
+           "solved": 9, "requests": 10, "latency_s": {"p50": 0.1, "p99": 1.0, "per_kind": {}},
+           "one_at_a_time": {"value": 1.0}, "oracle_verified": {"checked": 2, "verified": 2},
+           "roofline": None, "config": {"workload": "served stream", "batch_lanes": 2}}
+    s = bench.summary(out)
+    assert s["workload"] == "served stream"
+    assert s["oracle_verified"] == {"checked": 2, "verified": 2}
+    assert s["requests"] == 10 and s["latency_s"]["p99"] == 1.0
+    assert "roofline" not in s and "batch_lanes" not in s
