@@ -395,6 +395,8 @@ int create_impl(int64_t n, int64_t m, const int64_t* Qp, const int32_t* Qj, cons
     const int maxblk = std::max({S.Q.nblk, S.A.nblk, S.AT.nblk, S.R.nblk, VEC_GRID_MAX});   // partials slots
     if ((rc = dalloc(h, &S.partials, (size_t)maxblk * 8 * 2))) return bail(rc);
     S.partials2 = S.partials + (size_t)maxblk * 8;
+    if (S.qdiag && S.A.nlr > 0 && prox_diag_deferrable(S))
+        if ((rc = dalloc(h, &S.ylr, (size_t)2 * S.A.nlr))) return bail(rc);
     if (hipMemsetAsync(S.ctrl, 0, sizeof(Ctrl), h->own) != hipSuccess)
         return bail(fail(QP_ERR_DEVICE, "hipMemset failed"));
 
@@ -797,6 +799,9 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
     // reads it back after every check)
     long long t_round = 0;
     bool xbar_pending = false;   // the last x_bar kernel's finishing work is still to run
+    // closed-form path: the dual step of iteration lr_k (round step lr_t) left
+    // its long rows to the next primal kernel (-1: none)
+    long long lr_k = -1, lr_t = -1;
     int status = QP_NOT_SOLVED;
     for (;;) {
         if (k > 0 || p.max_iter == 0) {
@@ -831,7 +836,8 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
         const bool reduce = next_check || t_round == 0;
         if (S.qdiag) {
             Timed t(h, QP_FAM_RHS);
-            HIPCHK(launch_prox_diag(S, next_check, t_round, reduce, s));
+            HIPCHK(launch_prox_diag(S, next_check, t_round, reduce, lr_k, lr_t, s));
+            lr_k = lr_t = -1;
         } else {
             // the gradient is formed with a product with Q at the first
             // iteration and after every check (bounds the drift of the
@@ -849,7 +855,14 @@ int qp_solve_ex(qp_handle* h, const qp_params* params)
         {
             Timed t(h, QP_FAM_DUAL);
             const int pre = S.qdiag ? (prox_diag_deferrable(S) ? PRE_PROX : PRE_NONE) : PRE_XBAR;
-            HIPCHK(launch_dual(S, next_check, pre, t_round, k, reduce, s));
+            // a step whose reductions nothing reads leaves its long rows to
+            // the next primal kernel (never before a check: that iteration reduces)
+            const bool leave_long = S.ylr != nullptr && !reduce;
+            HIPCHK(launch_dual(S, next_check, pre, t_round, k, reduce, leave_long, s));
+            if (leave_long) {
+                lr_k = k;
+                lr_t = t_round;
+            }
             xbar_pending = !S.qdiag && !reduce;
         }
         ++k;

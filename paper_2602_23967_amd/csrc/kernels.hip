@@ -5,9 +5,11 @@
 //              a_ij * x_j in LDS with coalesced loads of values and column
 //              indices, then sums each row with a lane group sized to the
 //              block's row count (1..64 lanes, wavefront shuffles), and hands
-//              the row sum to the fused epilogue E.  Rows longer than NNZ_CAP
-//              are split into segments; each segment block stores its partial
-//              sum and the finishing kernel completes the row in segment order.
+//              the row sum to the fused epilogue E.  A row longer than NNZ_CAP
+//              and at most ROW_PASS_CAP long is one block's strided passes;
+//              longer rows are split into segments, each segment block stores
+//              its partial sum and a later kernel completes the row in
+//              segment order.
 //   k_vec<E>   grid-stride elementwise pass with epilogue E.
 // A kernel whose epilogue reduces scalars stores one partial per block
 // (wavefront xor-shuffle tree, then LDS across the block's 4 waves), and a
@@ -62,6 +64,38 @@ struct SumOne {
     __device__ static int kind(int) { return R_SUM; }
 };
 
+// sum of src[0, n) in exactly the order a FIN_T-thread finishing kernel
+// takes (strided per-thread sums, then block_reduce<SumOne, FIN_T>), with
+// TPB threads each standing in for FIN_T / TPB of those; the result is
+// valid on thread 0.  lds: at least FIN_T / 64 doubles.
+__device__ __forceinline__ double sum_in_fin_order(const double* src, int n, double* lds)
+{
+    constexpr int V = FIN_T / TPB;
+    static_assert(FIN_T % TPB == 0, "the finishing block is a multiple of TPB threads");
+    double v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        double a = 0.0;
+        for (int i = threadIdx.x + j * TPB; i < n; i += FIN_T) a += src[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        v[j] = a;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) lds[wave + j * (TPB / 64)] = v[j];
+    }
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = lds[0];
+        for (int w = 1; w < FIN_T / 64; ++w) r += lds[w];
+    }
+    __syncthreads();
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // the two kernel shapes
 // ---------------------------------------------------------------------------
@@ -81,6 +115,24 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
     constexpr bool F32 = std::is_same<T, float>::value;
     const BlkDesc d = M.blk[blockIdx.x];
     const int cnt = d.k1 - d.k0;
+    if (cnt > NNZ_CAP) {
+        // one row of up to ROW_PASS_CAP nonzeros: strided passes of the whole
+        // block (no staging), one block sum, the epilogue on thread 0
+        T ts = T(0);
+#pragma unroll 4
+        for (int q = threadIdx.x; q < cnt; q += TPB) {
+            const int j = M.col[d.k0 + q];
+            if constexpr (F32) ts += val[d.k0 + q] * e.xval32(j);
+            else ts += val[d.k0 + q] * e.xval(j);
+        }
+        double s[1] = {(double)ts};
+        block_reduce<SumOne>(s, lds);
+        if (threadIdx.x == 0) {
+            if constexpr (F32) e.row(d.row0, s[0] + e.rowref(d.row0), acc);
+            else e.row(d.row0, s[0], acc);
+        }
+        return;
+    }
     {
         int cj[NNZ_CAP / TPB];
         T av[NNZ_CAP / TPB];
@@ -140,6 +192,7 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
     E e = epi;
     if (e.skip()) return;
     e.init();
+    e.prologue(lds);
     const BlkDesc d = M.blk[blockIdx.x];
     double acc[NR];
 #pragma unroll
@@ -304,6 +357,7 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
                 double total = part[0];
                 if (e.use32()) total += e.rowref(row);
                 e.row(row, total, acc);
+                e.after_long_row(lr, row);
             }
         }
     }
@@ -315,6 +369,7 @@ __global__ __launch_bounds__(FIN_T) void k_spmv_fin(CsrDev M, E epi, const doubl
             for (int i = 0; i < nseg; ++i) total += M.seg_part[base + i];
             if (e.use32()) total += e.rowref(row);
             e.row(row, total, acc);
+            e.after_long_row(lr, row);
         }
     }
     if constexpr (E::NR > 0) {
@@ -398,6 +453,11 @@ struct EpiBase {
     __device__ double rowref(int) const { return 0.0; }
     __device__ static int kind(int) { return R_SUM; }
     __device__ void finalize(const double*) const {}
+    // work an earlier launch left to every block of this product, run before
+    // the block gathers its operand (all threads of the block call it)
+    __device__ void prologue(double*) const {}
+    // after a finishing kernel completed long row lr (row i)
+    __device__ void after_long_row(int, int) const {}
 };
 
 template <int N>
@@ -418,6 +478,114 @@ __device__ void inner_decide(Ctrl* c, double gp2, double b2, double ptp, long lo
     c->dir_mode = !prop ? DIR_BETA : (c->last_step == STEP_CG ? DIR_CONJ : DIR_PHI);
     post_status(dstat, seq, c->done);
 }
+
+// dual step (eq. dual_update) on the extrapolated point x_bar = 2 x_T - x
+// (eq. extrapolation), then the reflected Halpern average of y (Section 3.1)
+struct EpiDual : EpiBase {
+    static constexpr bool BULK = true;
+    static constexpr int NR = 4;
+    const double *xbar, *ya, *lc, *uc;
+    double *y, *yt, *ytil;
+    int store;
+    // mixed precision: A x_bar = A x_ref + A(x_bar - x_ref) (dxb32, axref), and
+    // y - y_ref is written for the next primal step's product
+    const float* dxb32 = nullptr;
+    const double *axref = nullptr, *yref = nullptr;
+    float* dy32 = nullptr;
+    __device__ bool use32() const { return dxb32 != nullptr; }
+    __device__ float xval32(int j) const { return dxb32[j]; }
+    __device__ double rowref(int i) const { return axref[i]; }
+    double sigma, w, wa, th;
+    int halpern;
+    // >= 0: the iteration count k and the round's step count t, given by the
+    // host (the closed-form path), else read from ctrl
+    long long tk = -1, kk = -1;
+    // closed-form path, A with long rows: y of the long rows after this
+    // step, in the slot of this iteration's parity (a step that leaves its
+    // long rows to the next primal kernel reads the other slot there)
+    double* ylr_out = nullptr;
+    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
+    __device__ void init()
+    {
+        sigma = ctrl->sigma;
+        const double t = (double)(tk >= 0 ? tk : ctrl->t);
+        w = (t + 1.0) / (t + 2.0);
+        wa = 1.0 / (t + 2.0);
+        th = ctrl->theta;
+        halpern = ctrl->use_halpern;
+    }
+    __device__ double xval(int j) const { return xbar[j]; }
+    // the dual step of row i from its product s and the previous y_i:
+    // returns the new y_i (Halpern average) and y_T,i in yti
+    __device__ double step(int i, double s, double yi, double& yti) const
+    {
+        const double l = lc[i], u = uc[i];
+        const double v = yi / sigma + s;
+        yti = sigma * (v - clampd(v, l, u));
+        return halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
+    }
+    __device__ void row(int i, double s, Acc<NR> a) const
+    {
+        const double yi = y[i];
+        double yti;
+        const double yn = step(i, s, yi, yti);
+        const double dy = yti - yi;
+        a[0] += dy * dy;
+        yt[i] = yti;
+        y[i] = yn;
+        if (dy32) dy32[i] = (float)(yn - yref[i]);
+        if (store) {
+            const double yy = projY(dy, lc[i], uc[i]);
+            ytil[i] = yy;
+            a[1] = rcomb(R_MAX, a[1], fabs(yy));
+            a[2] += supp(yy, lc[i], uc[i]);
+            a[3] += supp_abs(yy, lc[i], uc[i]);
+        }
+    }
+    __device__ void after_long_row(int lr, int i) const
+    {
+        if (ylr_out) ylr_out[lr] = y[i];
+    }
+    // long row lr (row i) of a step that left its long rows to the next
+    // primal kernel, completed there by every block: the previous y_i comes
+    // from the copy kept by the previous completion (y itself may already
+    // hold this step's value, stored by another block); every block stores
+    // y_i and its FP32 difference (the same values) before it gathers them,
+    // block 0 also y_T,i and the copy for the next completion.  No
+    // reductions: nothing reads them for such a step.
+    __device__ void long_row_late(int lr, int i, double s, const double* ylr_in, bool first) const
+    {
+        double yti;
+        const double yn = step(i, s, ylr_in[lr], yti);
+        y[i] = yn;
+        if (dy32) dy32[i] = (float)(yn - yref[i]);
+        if (first) {
+            yt[i] = yti;
+            ylr_out[lr] = yn;
+        }
+    }
+    // the last kernel of an iteration: the counters advance here, and the
+    // residual of the round's first step is kept for the restart test
+    __device__ void finalize(const double* t) const
+    {
+        Ctrl* C = ctrl;
+        C->ndy2 = t[0];
+        if (store) {
+            C->ytil_max = t[1];
+            C->ptil_sum = t[2];
+            C->ptil_abs = t[3];
+        }
+        if (tk >= 0) {
+            C->k = kk + 1;
+            C->t = tk + 1;
+        } else {
+            C->k += 1;
+            C->t += 1;
+        }
+        if (C->t == 1) C->R_start = sqrt(C->omega * C->ndx2 + C->ndy2 / C->omega);
+    }
+};
+
 
 // Reflected Halpern average of x (Section 3.1) for one row, fused into the
 // kernel that produces x_T: x <- w((1+theta) x_T - theta x) + wa x_anchor,
@@ -481,11 +649,45 @@ struct EpiProx : EpiBase {
     const double *atyref = nullptr, *xref = nullptr;
     float* dxb32 = nullptr;
     double it;
+    // lr_n > 0: the previous dual step (lrd) left its long rows to this
+    // kernel (an iteration whose reductions nothing reads: its one-block
+    // finishing kernel, which would only have completed them, did not run).
+    // Every block completes them from their segment partials, summed in the
+    // finishing kernel's order, before it gathers y.
+    EpiDual lrd;
+    const int* lr_info = nullptr;      // A's long rows: {row, first segment slot, segment count}
+    const double* lr_seg = nullptr;    // A's segment partials
+    const double* ylr_in = nullptr;    // y of the long rows before that step
+    int lr_n = 0, lr_coop = 0;
     __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
     __device__ void init()
     {
         it = ctrl->inv_tau;
         hx.init(ctrl);
+        if (lr_n > 0) lrd.init();
+    }
+    __device__ void prologue(double* lds) const
+    {
+        static_assert(NR * (TPB / 64) >= FIN_T / 64, "k_spmv's reduction buffer holds the ordered sum");
+        if (lr_n == 0) return;
+        const bool first = blockIdx.x == 0;
+        for (int lr = 0; lr < lr_coop; ++lr) {
+            const int row = lr_info[3 * lr], base = lr_info[3 * lr + 1], nseg = lr_info[3 * lr + 2];
+            const double part = sum_in_fin_order(lr_seg + base, nseg, lds);
+            if (threadIdx.x == 0) {
+                double total = part;
+                if (lrd.use32()) total += lrd.rowref(row);
+                lrd.long_row_late(lr, row, total, ylr_in, first);
+            }
+        }
+        for (int lr = lr_coop + threadIdx.x; lr < lr_n; lr += TPB) {
+            const int row = lr_info[3 * lr], base = lr_info[3 * lr + 1], nseg = lr_info[3 * lr + 2];
+            double total = 0.0;
+            for (int i = 0; i < nseg; ++i) total += lr_seg[base + i];
+            if (lrd.use32()) total += lrd.rowref(row);
+            lrd.long_row_late(lr, row, total, ylr_in, first);
+        }
+        __syncthreads();
     }
     __device__ double xval(int j) const { return y[j]; }
     __device__ bool use32() const { return dy32 != nullptr; }
@@ -790,79 +992,6 @@ struct EpiDir : EpiBase {
         const double pi = p[i];
         const Split sp = split(xt[i], g[i], lv.template at<BM>(i), uv.template at<BM>(i), abar);
         p[i] = mode == DIR_BETA ? sp.beta : (mode == DIR_PHI ? sp.phi : sp.phi - gam * pi);
-    }
-};
-
-// dual step (eq. dual_update) on the extrapolated point x_bar = 2 x_T - x
-// (eq. extrapolation), then the reflected Halpern average of y (Section 3.1)
-struct EpiDual : EpiBase {
-    static constexpr bool BULK = true;
-    static constexpr int NR = 4;
-    const double *xbar, *ya, *lc, *uc;
-    double *y, *yt, *ytil;
-    int store;
-    // mixed precision: A x_bar = A x_ref + A(x_bar - x_ref) (dxb32, axref), and
-    // y - y_ref is written for the next primal step's product
-    const float* dxb32 = nullptr;
-    const double *axref = nullptr, *yref = nullptr;
-    float* dy32 = nullptr;
-    __device__ bool use32() const { return dxb32 != nullptr; }
-    __device__ float xval32(int j) const { return dxb32[j]; }
-    __device__ double rowref(int i) const { return axref[i]; }
-    double sigma, w, wa, th;
-    int halpern;
-    // >= 0: the iteration count k and the round's step count t, given by the
-    // host (the closed-form path), else read from ctrl
-    long long tk = -1, kk = -1;
-    __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
-    __device__ void init()
-    {
-        sigma = ctrl->sigma;
-        const double t = (double)(tk >= 0 ? tk : ctrl->t);
-        w = (t + 1.0) / (t + 2.0);
-        wa = 1.0 / (t + 2.0);
-        th = ctrl->theta;
-        halpern = ctrl->use_halpern;
-    }
-    __device__ double xval(int j) const { return xbar[j]; }
-    __device__ void row(int i, double s, Acc<NR> a) const
-    {
-        const double yi = y[i], l = lc[i], u = uc[i];
-        const double v = yi / sigma + s;
-        const double yti = sigma * (v - clampd(v, l, u));
-        const double dy = yti - yi;
-        a[0] += dy * dy;
-        yt[i] = yti;
-        const double yn = halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
-        y[i] = yn;
-        if (dy32) dy32[i] = (float)(yn - yref[i]);
-        if (store) {
-            const double yy = projY(dy, l, u);
-            ytil[i] = yy;
-            a[1] = rcomb(R_MAX, a[1], fabs(yy));
-            a[2] += supp(yy, l, u);
-            a[3] += supp_abs(yy, l, u);
-        }
-    }
-    // the last kernel of an iteration: the counters advance here, and the
-    // residual of the round's first step is kept for the restart test
-    __device__ void finalize(const double* t) const
-    {
-        Ctrl* C = ctrl;
-        C->ndy2 = t[0];
-        if (store) {
-            C->ytil_max = t[1];
-            C->ptil_sum = t[2];
-            C->ptil_abs = t[3];
-        }
-        if (tk >= 0) {
-            C->k = kk + 1;
-            C->t = tk + 1;
-        } else {
-            C->k += 1;
-            C->t += 1;
-        }
-        if (C->t == 1) C->R_start = sqrt(C->omega * C->ndx2 + C->ndy2 / C->omega);
     }
 };
 
@@ -1263,9 +1392,11 @@ static int spmv_partial_blocks(const CsrDev& M) { return M.nparts > 1 ? vec_grid
 // launch no finishing kernel (the caller hands e to the next product's
 // finishing kernel as `pre`; only valid when the product has no long rows
 // to complete).  pre / pre_nblk: an earlier deferred epilogue finished first.
+// leave_long: the long rows are completed by the next kernel (no finishing
+// kernel at all when nothing reads this launch's reductions)
 template <class E, class Pre = NoPre>
 static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipStream_t s, bool defer = false,
-                           const Pre& pre = Pre{}, int pre_nblk = 0)
+                           const Pre& pre = Pre{}, int pre_nblk = 0, bool leave_long = false)
 {
     double* part = defer ? S.partials2 : S.partials;
     // e.reduce == 0: no finishing step, except the completion of long rows
@@ -1282,7 +1413,7 @@ static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipSt
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
     launch_spmv_main(M, e, part, s);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
-    if (fin || (M.nlr > 0 && !defer))
+    if (fin || (M.nlr > 0 && !defer && !leave_long))
         k_spmv_fin<E, Pre><<<1, FIN_T, 0, s>>>(M, e, part, pre, pre_nblk, S.partials2);
     return hipGetLastError();
 }
@@ -1334,11 +1465,25 @@ static EpiProx prox_epi(const DevState& S, int store_delta)
 // the product has no long rows to complete there.
 bool prox_diag_deferrable(const DevState& S) { return S.AT.nlr == 0; }
 
-hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, hipStream_t s)
+static EpiDual dual_epi(const DevState& S, int store_delta, long long tk, long long kk);
+
+hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, long long lr_k,
+                            long long lr_t, hipStream_t s)
 {
     EpiProx e = prox_epi(S, store_delta);
     e.hx.tk = tk;
     e.reduce = reduce ? 1 : 0;
+    if (lr_k >= 0) {
+        if (!S.ylr || S.A.nlr == 0) return hipErrorInvalidValue;
+        e.lrd = dual_epi(S, 0, lr_t, lr_k);
+        e.lrd.reduce = 0;
+        e.lrd.ylr_out = S.ylr + (size_t)((lr_k + 1) & 1) * S.A.nlr;
+        e.ylr_in = S.ylr + (size_t)(lr_k & 1) * S.A.nlr;
+        e.lr_info = S.A.lr_info;
+        e.lr_seg = S.A.seg_part;
+        e.lr_n = S.A.nlr;
+        e.lr_coop = S.A.nlr_coop;
+    }
     return run_spmv(S, S.AT, e, s, prox_diag_deferrable(S));
 }
 
@@ -1487,8 +1632,7 @@ hipError_t launch_clip(const DevState& S, double* x, hipStream_t s)
     return run_vec(S, S.n, e, s);
 }
 
-hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk, long long kk, bool reduce,
-                       hipStream_t s)
+static EpiDual dual_epi(const DevState& S, int store_delta, long long tk, long long kk)
 {
     EpiDual e{};
     e.ctrl = S.ctrl;
@@ -1496,12 +1640,22 @@ hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk
     e.y = S.y; e.yt = S.yt; e.ytil = S.ytil; e.store = store_delta;
     e.tk = tk;
     e.kk = kk;
-    e.reduce = reduce ? 1 : 0;
     if (S.mixed) { e.dxb32 = S.dxb32; e.axref = S.axref; e.yref = S.yref; e.dy32 = S.dy32; }
+    return e;
+}
+
+hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk, long long kk, bool reduce,
+                       bool leave_long, hipStream_t s)
+{
+    EpiDual e = dual_epi(S, store_delta, tk, kk);
+    e.reduce = reduce ? 1 : 0;
+    // the long rows' copy for a later step that leaves them (closed-form path)
+    if (S.ylr && kk >= 0) e.ylr_out = S.ylr + (size_t)((kk + 1) & 1) * S.A.nlr;
+    if (leave_long && (reduce || store_delta || pre != PRE_PROX || !S.ylr || kk < 0)) return hipErrorInvalidValue;
     if (pre == PRE_PROX) {
         EpiProx pe = prox_epi(S, store_delta);
         pe.hx.tk = tk;
-        return run_spmv(S, S.A, e, s, false, pe, spmv_partial_blocks(S.AT));
+        return run_spmv(S, S.A, e, s, false, pe, spmv_partial_blocks(S.AT), leave_long);
     }
     if (pre == PRE_XBAR) {
         EpiXbar xe = xbar_epi(S, store_delta);

@@ -127,6 +127,9 @@ struct DevState {
     Ctrl* ctrl = nullptr;
     double* partials = nullptr;
     double* partials2 = nullptr;   // partials of an epilogue whose finish is deferred
+    // closed-form path, A with long rows: y of A's long rows after the last
+    // dual step, two slots by iteration parity (2 x A.nlr)
+    double* ylr = nullptr;
     hipEvent_t* tev = nullptr;             // when set: events around the next main kernel
     unsigned long long* dstat = nullptr;   // pinned status word (device view)
     unsigned long long* dcheck = nullptr;  // pinned check result (device view)
@@ -140,8 +143,11 @@ hipError_t launch_init_start(const DevState& S, hipStream_t s);
 // step's finishing kernel when prox_diag_deferrable(S)
 // tk: the round's step count t from the host (>= 0) or -1 (read ctrl->t);
 // reduce = false: nothing reads this iteration's reductions (no partials,
-// and the dual step's finishing kernel only completes long rows)
-hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, hipStream_t s);
+// and the dual step's finishing kernel only completes long rows);
+// lr_k >= 0: the dual step of iteration lr_k (round step lr_t) left its long
+// rows, which this kernel's blocks complete first
+hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bool reduce, long long lr_k,
+                            long long lr_t, hipStream_t s);
 bool prox_diag_deferrable(const DevState& S);
 hipError_t launch_rhs(const DevState& S, hipStream_t s);
 hipError_t launch_ginit(const DevState& S, long long seq, hipStream_t s);
@@ -163,9 +169,12 @@ hipError_t launch_clip(const DevState& S, double* x, hipStream_t s); // x <- pro
 // dual step and Halpern on y; pre names the earlier epilogue whose finishing
 // work its finishing kernel runs first (same store_delta)
 enum { PRE_NONE = 0, PRE_PROX = 1, PRE_XBAR = 2 };
-// tk, kk: t and the iteration count k from the host (>= 0) or -1 (ctrl)
+// tk, kk: t and the iteration count k from the host (>= 0) or -1 (ctrl);
+// leave_long: the closed-form path's non-reducing step leaves its long rows
+// to the next launch_prox_diag (lr_k = kk, lr_t = tk) instead of a one-block
+// finishing kernel (needs !reduce, no store_delta, PRE_PROX and S.ylr)
 hipError_t launch_dual(const DevState& S, int store_delta, int pre, long long tk, long long kk, bool reduce,
-                       hipStream_t s);
+                       bool leave_long, hipStream_t s);
 // KKT pieces at (x, y); with `full` also the infeasibility certificates
 // (and, with `dinf`, the unboundedness ones) and the solver's decision
 hipError_t launch_check(const DevState& S, const double* x, const double* y, int full, int dinf,

@@ -122,7 +122,8 @@ int check_bounds(const char* name, int64_t len, const double* l, const double* u
 
 // ---------------------------------------------------------------------------
 // SpMV schedule: greedy row blocks of <= NNZ_CAP nonzeros and <= ROWS_CAP
-// rows; a row longer than NNZ_CAP becomes NNZ_CAP-sized segments
+// rows; a row longer than NNZ_CAP is an item of its own when it has at most
+// ROW_PASS_CAP nonzeros, else NNZ_CAP-sized segments
 // ---------------------------------------------------------------------------
 
 void build_plan(int64_t rows, const int64_t* rp, std::vector<BlkDesc>& blk, int& nlr, int& nseg_tot)
@@ -133,6 +134,11 @@ void build_plan(int64_t rows, const int64_t* rp, std::vector<BlkDesc>& blk, int&
     int64_t r = 0;
     while (r < rows) {
         const int64_t L = rp[r + 1] - rp[r];
+        if (L > NNZ_CAP && L <= ROW_PASS_CAP) {
+            blk.push_back({(int)r, 1, (int)rp[r], (int)rp[r + 1], 0, 0, 0, 0});
+            ++r;
+            continue;
+        }
         if (L > NNZ_CAP) {
             const int nseg = (int)((L + NNZ_CAP - 1) / NNZ_CAP);
             for (int s = 0; s < nseg; ++s) {

@@ -16,6 +16,10 @@ constexpr int TPB = 256;        // threads per block for every kernel
 #endif
 constexpr int NNZ_CAP = PDHCG_NNZ_CAP;   // nonzeros staged in LDS per row block
 constexpr int ROWS_CAP = 256;   // rows per row block (one thread per row at most)
+// a row of more than NNZ_CAP and at most ROW_PASS_CAP nonzeros is summed by
+// one block in strided passes (no segments, so no finishing step completes
+// it); longer rows are split into NNZ_CAP-sized segments
+constexpr int ROW_PASS_CAP = 4 * NNZ_CAP;
 // blocks of an elementwise pass at most: 4 per CU; each thread then takes
 // several elements (1024 measured 1.3 % faster on the n = 1e6 QP than 2048,
 // and 0.3 % faster than 512; the other workloads do not change)
@@ -58,7 +62,9 @@ constexpr int LR_SEG_SERIAL = 8;
 
 // One work item of the row-block SpMV schedule.
 //   nrows > 0            rows [row0, row0+nrows), nonzeros [k0, k1); for a
-//                        column-partitioned matrix `lr` is the column part
+//                        column-partitioned matrix `lr` is the column part;
+//                        k1 - k0 > NNZ_CAP only for a single row (nrows == 1)
+//                        of at most ROW_PASS_CAP nonzeros
 //   nrows == 0, nseg > 0 segment `seg` of long row row0 (nonzeros [k0, k1));
 //                        its partial sum lands in seg_part[seg_base + seg] and
 //                        the finishing kernel completes the row (long row lr)

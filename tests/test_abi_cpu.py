@@ -112,8 +112,9 @@ def test_null_handle_calls():
 
 @pytest.mark.parametrize("lengths", [
     [11] * 1000,                                   # short uniform rows
-    [0, 0, 3, 0, 5000, 1, 2048, 2049, 0, 7] * 3,   # empty, long and boundary rows
-    [1] * 300 + [300] * 20 + [4097] + [0] * 5,     # row cap, medium rows, a long row
+    [0, 0, 3, 0, 5000, 1, 2048, 2049, 0, 7] * 3,   # empty, one-block long and boundary rows
+    [1] * 300 + [300] * 20 + [4097] + [0] * 5,     # row cap, medium rows, a one-block long row
+    [3, 8192, 8193, 0, 20000, 2] * 2,              # the longest one-block row, segmented rows
     [],                                            # no rows
     [0] * 10,                                      # only empty rows
 ])
@@ -125,14 +126,14 @@ def test_spmv_schedule_covers_each_nonzero_once(lengths):
     seen_nnz = np.zeros(int(rp[-1]), int)
     seg_slots = set()
     for row0, nr, k0, k1, lr, seg, nseg, base in items:
-        assert 0 <= k1 - k0 <= 2048
+        assert 0 <= k1 - k0 <= 2048 or (nr == 1 and 2048 < k1 - k0 <= 8192)
         if nr > 0:
             assert nr <= 256
             assert k0 == rp[row0] and k1 == rp[row0 + nr]
             seen_rows[row0:row0 + nr] += 1
             seen_nnz[k0:k1] += 1
         elif nseg > 0:
-            assert lengths[row0] > 2048 and 0 <= seg < nseg
+            assert lengths[row0] > 8192 and 0 <= seg < nseg and k1 - k0 <= 2048
             assert rp[row0] <= k0 < k1 <= rp[row0 + 1]
             seen_nnz[k0:k1] += 1
             seg_slots.add(base + seg)

@@ -88,7 +88,8 @@ def test_spmv_parity_small(torch):
 
 def test_spmv_parity_ragged_rows(torch):
     """Row lengths straddling every schedule boundary: empty rows, 1..2048
-    nonzeros, 2049 (one extra segment), 5000 and 9000 (several segments)."""
+    nonzeros (row blocks), 2049 and 5000 (one block's strided passes), 9000
+    (segments)."""
     rng = np.random.default_rng(1)
     n = 9500
     lengths = [0, 1, 2, 3, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049, 5000, 9000, 0, 7, 300, 0]
