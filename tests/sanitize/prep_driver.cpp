@@ -61,7 +61,10 @@ int check_plan(const Csr& M)
     std::vector<int> seen(M.cj.size(), 0);
     int bad = 0;
     for (const BlkDesc& b : blk) {
-        if (b.nrows > ROWS_CAP || b.k1 - b.k0 > NNZ_CAP) ++bad;
+        if (b.nrows > ROWS_CAP) ++bad;
+        // a single row of up to ROW_PASS_CAP nonzeros may be one item
+        if (b.k1 - b.k0 > (b.nrows == 1 ? ROW_PASS_CAP : NNZ_CAP)) ++bad;
+        if (b.nrows == 0 && b.nseg > 0 && M.rp[b.row0 + 1] - M.rp[b.row0] <= ROW_PASS_CAP) ++bad;
         if (b.nrows > 0 && (b.k0 != M.rp[b.row0] || b.k1 != M.rp[b.row0 + b.nrows])) ++bad;
         for (int k = b.k0; k < b.k1; ++k) seen[k]++;
     }
