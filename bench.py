@@ -353,7 +353,7 @@ def main_portfolio(args, torch, P, I):
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         # the plain FP64 form on the same GPU, and the result's error against it
-        p64 = P.qp_params_default(tol=args.tol, max_iter=args.max_iter)
+        p64 = P.qp_params_default(tol=args.tol, timing=args.timing, max_iter=args.max_iter)
         a = time.perf_counter()
         P.qp_solve_ex(h, p64)
         t64 = time.perf_counter() - a
@@ -549,7 +549,9 @@ def parser():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--timing", type=int, default=4, help="time every k-th launch per kernel family")
+    ap.add_argument("--timing", type=int, default=64,
+                    help="time every k-th launch per kernel family with HIP events (each timed launch "
+                         "costs about 7 us of event records; 64 keeps that near 0.5%% of a solve)")
     ap.add_argument("--lag", type=int, default=1, help="inner steps queued ahead of the host's view")
     ap.add_argument("--max-iter", type=int, default=100000,
                     help="outer iteration cap (lower only for short profiling runs)")

@@ -515,14 +515,18 @@ struct EpiDual : EpiBase {
         halpern = ctrl->use_halpern;
     }
     __device__ double xval(int j) const { return xbar[j]; }
-    // the dual step of row i from its product s and the previous y_i:
-    // returns the new y_i (Halpern average) and y_T,i in yti
-    __device__ double step(int i, double s, double yi, double& yti) const
+    // the dual step of a row from its product s, the previous y_i, the
+    // row's bounds and anchor: returns the new y_i (Halpern average) and y_T,i
+    // in yti
+    __device__ double step_v(double s, double yi, double l, double u, double yai, double& yti) const
     {
-        const double l = lc[i], u = uc[i];
         const double v = yi / sigma + s;
         yti = sigma * (v - clampd(v, l, u));
-        return halpern ? w * ((1.0 + th) * yti - th * yi) + wa * ya[i] : yti;
+        return halpern ? w * ((1.0 + th) * yti - th * yi) + wa * yai : yti;
+    }
+    __device__ double step(int i, double s, double yi, double& yti) const
+    {
+        return step_v(s, yi, lc[i], uc[i], ya[i], yti);
     }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
@@ -557,8 +561,12 @@ struct EpiDual : EpiBase {
     {
         double yti;
         const double yn = step(i, s, ylr_in[lr], yti);
+        store_late(lr, i, yn, yti, dy32 ? yref[i] : 0.0, first);
+    }
+    __device__ void store_late(int lr, int i, double yn, double yti, double yrefi, bool first) const
+    {
         y[i] = yn;
-        if (dy32) dy32[i] = (float)(yn - yref[i]);
+        if (dy32) dy32[i] = (float)(yn - yrefi);
         if (first) {
             yt[i] = yti;
             ylr_out[lr] = yn;
@@ -659,6 +667,7 @@ struct EpiProx : EpiBase {
     const double* lr_seg = nullptr;    // A's segment partials
     const double* ylr_in = nullptr;    // y of the long rows before that step
     int lr_n = 0, lr_coop = 0;
+    int lr0[3] = {-1, 0, 0};           // lr_info of long row 0 (one of the block-summed rows)
     __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
     __device__ void init()
     {
@@ -671,7 +680,31 @@ struct EpiProx : EpiBase {
         static_assert(NR * (TPB / 64) >= FIN_T / 64, "k_spmv's reduction buffer holds the ordered sum");
         if (lr_n == 0) return;
         const bool first = blockIdx.x == 0;
-        for (int lr = 0; lr < lr_coop; ++lr) {
+        if (lr_coop > 0) {
+            // long row 0 (a budget row, a dense row): its own values are
+            // loaded while its segment partials are summed
+            const int row = lr0[0];
+            double l = 0.0, u = 0.0, yai = 0.0, yi = 0.0, ref = 0.0, yrefi = 0.0;
+            if (threadIdx.x == 0) {
+                l = lrd.lc[row];
+                u = lrd.uc[row];
+                yai = lrd.ya[row];
+                yi = ylr_in[0];
+                if (lrd.use32()) {
+                    ref = lrd.rowref(row);
+                    yrefi = lrd.yref[row];
+                }
+            }
+            const double part = sum_in_fin_order(lr_seg + lr0[1], lr0[2], lds);
+            if (threadIdx.x == 0) {
+                double total = part;
+                if (lrd.use32()) total += ref;
+                double yti;
+                const double yn = lrd.step_v(total, yi, l, u, yai, yti);
+                lrd.store_late(0, row, yn, yti, yrefi, first);
+            }
+        }
+        for (int lr = 1; lr < lr_coop; ++lr) {
             const int row = lr_info[3 * lr], base = lr_info[3 * lr + 1], nseg = lr_info[3 * lr + 2];
             const double part = sum_in_fin_order(lr_seg + base, nseg, lds);
             if (threadIdx.x == 0) {
@@ -1222,7 +1255,11 @@ struct EpiQx : EpiBase {
         C->restart_pending = restart;
         C->pinf = st == 2;
         C->dinf = st == 3;
-        post_status(dcheck, C->checks, st != 0);
+        // the host's view of the decision: check count, restart, stop
+        __hip_atomic_store(dcheck,
+                           (static_cast<unsigned long long>(C->checks) << 2) | (restart ? 2ull : 0ull) |
+                               (st != 0 ? 1ull : 0ull),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 };
 
@@ -1483,6 +1520,7 @@ hipError_t launch_prox_diag(const DevState& S, int store_delta, long long tk, bo
         e.lr_seg = S.A.seg_part;
         e.lr_n = S.A.nlr;
         e.lr_coop = S.A.nlr_coop;
+        for (int j = 0; j < 3; ++j) e.lr0[j] = S.A.lr0[j];
     }
     return run_spmv(S, S.AT, e, s, prox_diag_deferrable(S));
 }

@@ -24,6 +24,7 @@ struct CsrDev {
     int* lr_info = nullptr;    // per long row: {row, first segment slot, segment count}
     int nlr = 0;
     int nlr_coop = 0;          // the first nlr_coop long rows are summed by the whole block
+    int lr0[3] = {-1, 0, 0};   // lr_info of the first long row (kernels read it without a load)
 };
 
 // inner-solver direction kinds
@@ -132,7 +133,8 @@ struct DevState {
     double* ylr = nullptr;
     hipEvent_t* tev = nullptr;             // when set: events around the next main kernel
     unsigned long long* dstat = nullptr;   // pinned status word (device view)
-    unsigned long long* dcheck = nullptr;  // pinned check result (device view)
+    // pinned check result (device view): (checks << 2) | restart << 1 | stop
+    unsigned long long* dcheck = nullptr;
 };
 
 // ---- launchers (kernels.hip) ------------------------------------------------
