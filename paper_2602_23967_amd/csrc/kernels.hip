@@ -118,6 +118,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
     if (cnt > NNZ_CAP) {
         // one row of up to ROW_PASS_CAP nonzeros: strided passes of the whole
         // block (no staging), one block sum, the epilogue on thread 0
+        e.prologue(lds);
         T ts = T(0);
 #pragma unroll 4
         for (int q = threadIdx.x; q < cnt; q += TPB) {
@@ -142,6 +143,9 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
             cj[i] = q < cnt ? M.col[d.k0 + q] : -1;
             av[i] = q < cnt ? val[d.k0 + q] : T(0);
         }
+        // work an earlier launch left to this block, before its gathers:
+        // its loads overlap the block's own column and value loads
+        e.prologue(lds);
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
@@ -192,7 +196,6 @@ __global__ __launch_bounds__(TPB) void k_spmv(CsrDev M, E epi, double* partials)
     E e = epi;
     if (e.skip()) return;
     e.init();
-    e.prologue(lds);
     const BlkDesc d = M.blk[blockIdx.x];
     double acc[NR];
 #pragma unroll
