@@ -245,6 +245,10 @@ def main_batch(args, torch, P, I):
         log(f"step {s_}: {int(np.sum(st == P.OPTIMAL))}/{len(qs)} optimal in {lat[-1] * 1e3:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    # the last launch's per-instance times (device wall clock): when each
+    # instance finished after the launch's first instance was taken up, and
+    # how long its workgroup took over it
+    t_take, t_done = bs.times()
     infos = [bs.result(i).info for i in range(len(qs))]
     iters = [i["iterations"] for i in infos]
     col_b = 2 if max(max(q.n, q.m) for q in qs) <= 65536 else 4
@@ -280,6 +284,15 @@ def main_batch(args, torch, P, I):
                    "instances": len(qs)},
         "solved": bool(np.all(st == P.OPTIMAL)),
         "solved_count": int(n_ok),
+        "instance_times_ms": {
+            "completion_p50": 1e3 * float(np.percentile(t_done, 50)),
+            "completion_p99": 1e3 * float(np.percentile(t_done, 99)),
+            "completion_max": 1e3 * float(np.max(t_done)),
+            "solve_p50": 1e3 * float(np.percentile(t_done - t_take, 50)),
+            "solve_p99": 1e3 * float(np.percentile(t_done - t_take, 99)),
+            "solve_max": 1e3 * float(np.max(t_done - t_take)),
+            "note": "last timed launch; completion = finish time after the launch's first instance was taken up, "
+                    "solve = the workgroup's time on the instance (device wall clock)"},
         "iterations": {"mean": float(np.mean(iters)), "max": int(np.max(iters))},
         "roofline": {"bound": "hbm", "achieved": nbytes / kernel_s / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": nbytes / kernel_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
@@ -776,7 +789,8 @@ def summary(out):
     """The figures of a workload's line that the default run attaches for
     the other workloads (measured in the same run)."""
     keep = ("value", "unit", "ms_per_step", "steps", "dtype", "solved", "solved_count", "requests", "iterations",
-            "latency_s", "latency_us", "fp64_plain", "one_at_a_time", "error_vs_fp64", "oracle_verified")
+            "latency_s", "latency_us", "fp64_plain", "one_at_a_time", "error_vs_fp64", "oracle_verified",
+            "instance_times_ms")
     d = {k: out[k] for k in keep if k in out}
     d["workload"] = out["config"]["workload"]
     r = out.get("roofline")

@@ -272,6 +272,14 @@ int qp_batch_result(const qp_batch* bt, int64_t i, double* x, double* y, qp_info
  * time in seconds (may be NULL). */
 int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds);
 
+/* When each instance of the last solve was taken up by a workgroup and
+ * when it finished, in seconds after the first instance was taken up
+ * (device wall clock; host buffers of count entries, either may be NULL):
+ * the instances' completion times inside the one persistent launch.
+ * Returns 0, QP_ERR_STATE before a solve, QP_ERR_DEVICE when the device
+ * reports no wall clock rate. */
+int qp_batch_times(const qp_batch* bt, double* start_s, double* end_s);
+
 void qp_batch_destroy(qp_batch* bt);
 
 /* ---- batched solve without device allocation ---------------------------

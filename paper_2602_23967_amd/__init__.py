@@ -129,6 +129,7 @@ def lib():
         L.qp_batch_solve.argtypes = [C.c_void_p, C.POINTER(QPParams)]
         L.qp_batch_result.argtypes = [C.c_void_p, _i64, _dp, _dp, C.POINTER(QPInfo)]
         L.qp_batch_statuses.argtypes = [C.c_void_p, _ip, _dp]
+        L.qp_batch_times.argtypes = [C.c_void_p, _dp, _dp]
         L.qp_batch_destroy.argtypes = [C.c_void_p]
         L.qp_batch_destroy.restype = None
         L.qp_batch_solve_static.argtypes = [_i64, _lp, _lp, _lp, _ip, _dp, _lp, _ip, _dp, _dp, _dp,
@@ -485,6 +486,15 @@ def _is_diagonal(Q) -> bool:
     return bool(np.all(r == c_))
 
 
+def qp_batch_times(h, count):
+    """(start, end) seconds of each instance of the last solve, after the
+    first instance was taken up (device wall clock)."""
+    t0 = np.zeros(count)
+    t1 = np.zeros(count)
+    _check(lib().qp_batch_times(h, _d(t0), _d(t1)))
+    return t0, t1
+
+
 class BatchSolver:
     """Owns a batch of instances.QP objects (diagonal or zero Q each)."""
 
@@ -504,6 +514,10 @@ class BatchSolver:
         q = self.qps[i]
         st, x, y, info = qp_batch_result(self.h, i, q.n, q.m)
         return Result(st, x, y, info)
+
+    def times(self):
+        """(start, end) seconds of each instance of the last solve."""
+        return qp_batch_times(self.h, len(self.qps))
 
     def set_schedule(self, shape=-1, order=-1):
         qp_batch_set_schedule(self.h, shape, order)

@@ -308,6 +308,7 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
     const int v0 = uniform_int(B.voff[b]), n = uniform_int(B.voff[b + 1]) - v0;
     const int r0 = uniform_int(B.roff[b]), m = uniform_int(B.roff[b + 1]) - r0;
     const int tid = threadIdx.x;
+    const unsigned long long t_start = wall_clock64();
     double* x = B.x + v0;   double* xa = B.xa + v0; double* xt = B.xt + v0;
     double* xbar = B.xbar;  double* aty = B.aty + v0; double* d = B.d + v0;
     const double* c = B.c + v0; const double* qd = B.qd + v0;
@@ -695,6 +696,8 @@ __device__ __forceinline__ void batch_solve_one(const BatchDev& B, const BatchPa
         o.r_primal = rp_; o.r_dual = rd_; o.r_gap = rg_;
         o.pobj = pobj; o.dobj = dobj; o.omega = omega;
         o.ytil_max = ytil_max; o.d_max = d_max;
+        o.t_start = t_start;
+        o.t_end = wall_clock64();
         B.out[b] = o;
     }
     __syncthreads();

@@ -1596,6 +1596,24 @@ int qp_batch_statuses(const qp_batch* bt, int32_t* status, double* seconds)
     return 0;
 }
 
+int qp_batch_times(const qp_batch* bt, double* start_s, double* end_s)
+{
+    if (!bt) return fail(QP_ERR_INVALID_ARG, "batch is NULL");
+    if (!bt->solved) return fail(QP_ERR_STATE, "no solve has run on this batch");
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        khz <= 0)
+        return fail(QP_ERR_DEVICE, "device wall clock rate unavailable");
+    unsigned long long t0 = ~0ull;
+    for (const BatchOut& o : bt->out) t0 = std::min(t0, o.t_start);
+    const double tick = 1.0 / (1e3 * (double)khz);
+    for (int64_t i = 0; i < bt->count; ++i) {
+        if (start_s) start_s[i] = (double)(bt->out[i].t_start - t0) * tick;
+        if (end_s) end_s[i] = (double)(bt->out[i].t_end - t0) * tick;
+    }
+    return 0;
+}
+
 int64_t qp_spmv_schedule(int64_t rows, const int64_t* rowptr, int32_t* out, int64_t cap)
 {
     if (rows < 0 || !rowptr) return fail(QP_ERR_INVALID_ARG, "bad argument");

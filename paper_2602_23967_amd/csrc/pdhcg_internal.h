@@ -219,6 +219,9 @@ struct BatchOut {
     int status, pad;
     long long iterations, restarts, inner_iterations;
     double r_primal, r_dual, r_gap, pobj, dobj, omega, ytil_max, d_max;
+    // device wall clock (wall_clock64 ticks) when a workgroup took the
+    // instance and when it finished it
+    unsigned long long t_start, t_end;
 };
 
 struct BatchParams {

@@ -75,6 +75,26 @@ def test_batch_matches_oracle(torch, mix):
     assert list(st) == [r.status for r in res]
 
 
+def test_batch_instance_times(torch):
+    """Per-instance times of a persistent launch: the first instance is
+    taken up at 0, every instance finishes after it was taken up, and the
+    last finish lies within the launch's host-measured wall time."""
+    qs = [I.mpc(i) for i in range(300)]
+    with P.BatchSolver(qs) as bs:
+        with pytest.raises(P.QPError):
+            bs.times()   # before any solve
+        a = time.perf_counter()
+        st, secs = bs.solve()
+        wall = time.perf_counter() - a
+        t0, t1 = bs.times()
+    print(f"300 instances: wall {wall * 1e3:.1f} ms, last finish {t1.max() * 1e3:.1f} ms, "
+          f"median solve {np.median(t1 - t0) * 1e3:.2f} ms", flush=True)
+    assert np.all(st == P.OPTIMAL)
+    assert t0.min() == 0.0
+    assert np.all(np.isfinite(t0)) and np.all(np.isfinite(t1)) and np.all(t1 > t0)
+    assert t1.max() <= wall
+
+
 def test_batch_alone_equals_in_the_mix(torch, mix):
     """An instance's result does not depend on the other instances of the
     launch (bitwise)."""
