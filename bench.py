@@ -547,9 +547,30 @@ def verify_served(qs, res, args, P):
                      "verified": bool(good)})
         log(f"verify request {i} ({q.name}): {rows[-1]['status']} vs oracle {rows[-1]['oracle_status']}, "
             f"kkt {kkt}, objective error {ferr}: {'ok' if good else 'MISMATCH'}")
+    oracle_s = time.perf_counter() - t0
+    # the same checked requests solved again by the oracle on one thread
+    # (standalone serve runs; the default line skips it)
+    single = None
+    if getattr(args, "verify_single_thread", False) and rows:
+        nth = oracle.num_threads()
+        oracle.set_num_threads(1)
+        t1, done = time.perf_counter(), 0
+        try:
+            for r in rows:
+                if time.perf_counter() - t1 > args.verify_budget_s:
+                    break
+                q = qs[r["request"]]
+                oracle.solve(q, tol=1e-9 if q.n <= 20000 else 1e-7, max_iter=1_000_000)
+                done += 1
+        finally:
+            oracle.set_num_threads(nth)
+        el1 = time.perf_counter() - t1
+        single = {"requests": done, "seconds": el1, "cores": 1,
+                  "note": f"the first {done} checked requests again on one thread (the 16-thread pass above "
+                          f"took {oracle_s:.1f} s for all {len(rows)})"}
     return {"selected": len(order), "checked": len(rows), "verified": sum(r["verified"] for r in rows),
             "by_kind": {k: {"checked": v[0], "verified": v[1]} for k, v in by_kind.items()},
-            "oracle_seconds": time.perf_counter() - t0, "cores": oracle.num_threads(),
+            "oracle_seconds": oracle_s, "cores": oracle.num_threads(), "single_thread": single,
             "sample": f"seeded 5% of {len(qs)} requests (seed {SERVE_VERIFY_SEED}) plus every infeasible request, "
                       f"smallest first, {args.verify_budget_s:g}s oracle budget",
             "mismatches": [r for r in rows if not r["verified"]]}
@@ -607,6 +628,8 @@ def parser():
                     help="default workload only: skip the other workloads' figures")
     ap.add_argument("--verify-budget-s", type=float, default=90.0,
                     help="oracle time for verifying the served stream's sample")
+    ap.add_argument("--no-verify-single-thread", dest="verify_single_thread", action="store_false",
+                    help="serve: skip timing the verified sample again on one oracle thread")
     return ap
 
 
@@ -819,6 +842,7 @@ def run_secondary(args, torch, P, I):
             a.no_cpu_baseline = args.no_cpu_baseline
             a.verify_budget_s = min(args.verify_budget_s, 45.0)
             a.one_at_a_time_s = min(args.one_at_a_time_s, 15.0)
+            a.verify_single_thread = False
         t = time.perf_counter()
         out = runs[wl](a, torch, P, I)
         res[wl] = summary(out)

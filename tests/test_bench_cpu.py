@@ -82,7 +82,11 @@ def test_verify_served_accepts_and_flags():
     res = _served_results(qs)
     v = bench.verify_served(qs, res, args, P)
     assert v["selected"] == 2 and v["checked"] == 2 and v["verified"] == 2, v
-    assert v["mismatches"] == []
+    assert v["mismatches"] == [] and v["single_thread"] is None
+    args1 = types.SimpleNamespace(verify_budget_s=120.0, tol=1e-6, verify_single_thread=True)
+    v1 = bench.verify_served(qs, res, args1, P)
+    assert v1["verified"] == 2 and v1["single_thread"]["requests"] == 2
+    assert v1["single_thread"]["cores"] == 1
     assert res[19][0].status == P.PRIMAL_INFEASIBLE
     # the sampled request (the one that is not the infeasible one)
     rng = np.random.default_rng(bench.SERVE_VERIFY_SEED)
