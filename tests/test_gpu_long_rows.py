@@ -88,6 +88,24 @@ def test_iterates_match_oracle(torch, qp, iters):
         assert err <= 1e-9, (what, err)
 
 
+@pytest.mark.parametrize("every", [2, 3, 5])
+def test_iterates_match_oracle_short_rounds(torch, qp, every):
+    """Checks every 2, 3 or 5 iterations: rounds of one or a few steps that
+    leave long rows, restarts that reset the round right after a completion,
+    and the full finishing kernel before every check, in quick alternation."""
+    with P.Solver(qp) as s:
+        g = s.solve(max_iter=150, check_every=every)
+    o = oracle.solve(qp, max_iter=150, check_every=every)
+    assert g.status == o.status
+    assert g.info["iterations"] == o.info["iterations"]
+    assert g.info["restarts"] == o.info["restarts"]
+    for a, r, what in ((g.x, o.x, "x"), (g.y, o.y, "y")):
+        err = np.abs(a - r).max() / (1.0 + np.abs(r).max())
+        print(f"check every {every}: {what} max relative difference {err:.2e}, "
+              f"restarts {g.info['restarts']}", flush=True)
+        assert err <= 1e-9, (what, err)
+
+
 @pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
 def test_solve_matches_oracle(torch, qp, precision):
     with P.Solver(qp) as s:
