@@ -326,6 +326,25 @@ def test_iteration_limits_and_start_point(torch):
     assert g1.status == P.ITERATION_LIMIT and g1.info["iterations"] == 1
 
 
+@pytest.mark.parametrize("every", [3, 64])
+def test_general_q_iterates_match_oracle(torch, every):
+    """The MPRGP path after a fixed number of iterations, with checks every
+    3 (many restarts, the round's step count reset by the check's posted
+    decision) or every 64 iterations: the same inner and restart counts as
+    the oracle and the same iterates up to rounding order."""
+    q = I.random_small(0)
+    g = _gpu_solve(q, max_iter=150, check_every=every)
+    o = oracle.solve(q, max_iter=150, check_every=every)
+    assert g.status == o.status
+    for key in ("iterations", "inner_iterations", "restarts"):
+        assert g.info[key] == o.info[key], key
+    for a, r, what in ((g.x, o.x, "x"), (g.y, o.y, "y")):
+        err = np.abs(a - r).max() / (1.0 + np.abs(r).max())
+        print(f"every {every}: {what} max relative difference {err:.2e}, restarts {g.info['restarts']}, "
+              f"inner {g.info['inner_iterations']}", flush=True)
+        assert err <= 1e-10, (what, err)
+
+
 def test_no_rows_and_lp(torch):
     q = I.tiny(21, n=5, m=1)
     q.A = q.A[:0]
