@@ -75,6 +75,24 @@ def test_batch_matches_oracle(torch, mix):
     assert list(st) == [r.status for r in res]
 
 
+def test_batch_iterates_match_oracle(torch):
+    """Each instance's iterates after 150 iterations (checks every 5, so
+    several restarts) equal the oracle's up to rounding order, in FP64: the
+    persistent kernel runs the same steps and decisions per instance."""
+    qs = [I.mpc(i) for i in range(6)] + [I.portfolio(1, n_assets=240, k_factors=3)]
+    with P.BatchSolver(qs) as bs:
+        st, _ = bs.solve(max_iter=150, check_every=5)
+        res = [bs.result(i) for i in range(len(qs))]
+    for q, g in zip(qs, res):
+        o = oracle.solve(q, max_iter=150, check_every=5)
+        assert g.status == o.status, q.name
+        assert g.info["iterations"] == o.info["iterations"] and g.info["restarts"] == o.info["restarts"], q.name
+        err = max(np.abs(g.x - o.x).max() / (1.0 + np.abs(o.x).max()),
+                  np.abs(g.y - o.y).max() / (1.0 + np.abs(o.y).max()))
+        print(f"{q.name}: restarts {g.info['restarts']}, max relative difference {err:.2e}", flush=True)
+        assert err <= 1e-10, (q.name, err)
+
+
 def test_batch_instance_times(torch):
     """Per-instance times of a persistent launch: the first instance is
     taken up at 0, every instance finishes after it was taken up, and the
