@@ -66,6 +66,26 @@ def test_factored_solve_matches_oracle(torch, make):
     assert abs(f - fr) <= 1e-6 * (1 + abs(fr))
 
 
+@pytest.mark.parametrize("every", [3, 64])
+def test_factored_iterates_match_oracle(torch, every):
+    """Q given as P + R'R (never formed) against the oracle on the explicit
+    Q, after 150 iterations: the same inner and restart counts, the same
+    iterates up to the order of the products' sums."""
+    q = I.random_factored(0)
+    e = q.explicit()
+    with P.Solver(q) as s:
+        g = s.solve(max_iter=150, check_every=every)
+    o = oracle.solve(e, max_iter=150, check_every=every)
+    assert g.status == o.status
+    for key in ("iterations", "inner_iterations", "restarts"):
+        assert g.info[key] == o.info[key], key
+    for a, r, what in ((g.x, o.x, "x"), (g.y, o.y, "y")):
+        err = np.abs(a - r).max() / (1.0 + np.abs(r).max())
+        print(f"every {every}: {what} max relative difference {err:.2e}, restarts {g.info['restarts']}, "
+              f"inner {g.info['inner_iterations']}", flush=True)
+        assert err <= 1e-10, (what, err)
+
+
 def test_factored_mixed_precision(torch):
     q = I.random_factored(4)
     e = q.explicit()
