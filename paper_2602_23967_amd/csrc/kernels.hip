@@ -118,7 +118,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
     if (cnt > NNZ_CAP) {
         // one row of up to ROW_PASS_CAP nonzeros: strided passes of the whole
         // block (no staging), one block sum, the epilogue on thread 0
-        e.prologue(lds);
+        e.template prologue<F32>(lds);
         T ts = T(0);
 #pragma unroll 4
         for (int q = threadIdx.x; q < cnt; q += TPB) {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
         }
         // work an earlier launch left to this block, before its gathers:
         // its loads overlap the block's own column and value loads
-        e.prologue(lds);
+        e.template prologue<F32>(lds);
 #pragma unroll
         for (int i = 0; i < NNZ_CAP / TPB; ++i) {
             const int q = threadIdx.x + i * TPB;
@@ -457,7 +457,9 @@ struct EpiBase {
     __device__ static int kind(int) { return R_SUM; }
     __device__ void finalize(const double*) const {}
     // work an earlier launch left to every block of this product, run before
-    // the block gathers its operand (all threads of the block call it)
+    // the block gathers its operand (all threads of the block call it);
+    // F32: the block gathers the FP32 operand
+    template <bool F32>
     __device__ void prologue(double*) const {}
     // after a finishing kernel completed long row lr (row i)
     __device__ void after_long_row(int, int) const {}
@@ -671,17 +673,29 @@ struct EpiProx : EpiBase {
     const double* ylr_in = nullptr;    // y of the long rows before that step
     int lr_n = 0, lr_coop = 0;
     int lr0[3] = {-1, 0, 0};           // lr_info of long row 0 (one of the block-summed rows)
+    // mixed precision: long row 0's FP32 difference y - y_ref, held by every
+    // thread of the block, which gathers it from here (the FP32 product
+    // gathers nothing else of y), so only block 0 stores that row's values;
+    // a store from every block into the line the others gather from cost
+    // the mixed kernel 1.6 % of a solve.  FP64 gathers y itself: there every
+    // block stores the row's new y (a select per gather measured slower).
+    int lr0_live = -1;
+    mutable float lr0_d32 = 0.0f;
     __device__ static int kind(int j) { return j == 1 ? R_MAX : R_SUM; }
     __device__ void init()
     {
         it = ctrl->inv_tau;
         hx.init(ctrl);
         if (lr_n > 0) lrd.init();
+        lr0_live = (lr_n > 0 && lr_coop > 0 && lrd.dy32 != nullptr) ? lr0[0] : -1;
     }
+    template <bool F32>
     __device__ void prologue(double* lds) const
     {
-        static_assert(NR * (TPB / 64) >= FIN_T / 64, "k_spmv's reduction buffer holds the ordered sum");
+        static_assert(NR * (TPB / 64) >= FIN_T / 64 + 1,
+                      "k_spmv's reduction buffer holds the ordered sum and long row 0's value");
         if (lr_n == 0) return;
+        const bool keep0 = F32 && lr0_live >= 0;   // long row 0's FP32 value kept in registers
         const bool first = blockIdx.x == 0;
         if (lr_coop > 0) {
             // long row 0 (a budget row, a dense row): its own values are
@@ -704,7 +718,8 @@ struct EpiProx : EpiBase {
                 if (lrd.use32()) total += ref;
                 double yti;
                 const double yn = lrd.step_v(total, yi, l, u, yai, yti);
-                lrd.store_late(0, row, yn, yti, yrefi, first);
+                if (first || !keep0) lrd.store_late(0, row, yn, yti, yrefi, first);
+                if (keep0) lds[FIN_T / 64] = (double)(float)(yn - yrefi);
             }
         }
         for (int lr = 1; lr < lr_coop; ++lr) {
@@ -724,10 +739,11 @@ struct EpiProx : EpiBase {
             lrd.long_row_late(lr, row, total, ylr_in, first);
         }
         __syncthreads();
+        if (keep0) lr0_d32 = (float)lds[FIN_T / 64];
     }
     __device__ double xval(int j) const { return y[j]; }
     __device__ bool use32() const { return dy32 != nullptr; }
-    __device__ float xval32(int j) const { return dy32[j]; }
+    __device__ float xval32(int j) const { return j == lr0_live ? lr0_d32 : dy32[j]; }
     __device__ double rowref(int i) const { return atyref[i]; }
     __device__ void row(int i, double s, Acc<NR> a) const
     {
@@ -1414,10 +1430,12 @@ int vec_grid(long long len)
 }
 
 template <class E>
-static void launch_spmv_main(const CsrDev& M, const E& e, double* partials, hipStream_t s)
+// the FP32 form only in a mixed-precision solve (a matrix keeps its FP32
+// copy after one; an FP64 solve then still runs the FP64-only kernel)
+static void launch_spmv_main(const CsrDev& M, const E& e, double* partials, bool mixed, hipStream_t s)
 {
     if constexpr (E::BULK) {
-        if (M.val32) {
+        if (M.val32 && mixed) {
             k_spmv<E, true><<<M.nblk, TPB, 0, s>>>(M, e, partials);
             return;
         }
@@ -1444,14 +1462,14 @@ static hipError_t run_spmv(const DevState& S, const CsrDev& M, const E& e, hipSt
     if (M.nparts > 1) {
         const int grid = vec_grid(M.rows);
         if (S.tev) (void)hipEventRecord(S.tev[0], s);
-        launch_spmv_main(M, e, part, s);
+        launch_spmv_main(M, e, part, S.mixed != 0, s);
         k_rows<E><<<grid, TPB, 0, s>>>(M, e, part);
         if (S.tev) (void)hipEventRecord(S.tev[1], s);
         if (fin) k_vec_fin<E, Pre><<<1, FIN_T, 0, s>>>(grid, e, part, pre, pre_nblk, S.partials2);
         return hipGetLastError();
     }
     if (S.tev) (void)hipEventRecord(S.tev[0], s);
-    launch_spmv_main(M, e, part, s);
+    launch_spmv_main(M, e, part, S.mixed != 0, s);
     if (S.tev) (void)hipEventRecord(S.tev[1], s);
     if (fin || (M.nlr > 0 && !defer && !leave_long))
         k_spmv_fin<E, Pre><<<1, FIN_T, 0, s>>>(M, e, part, pre, pre_nblk, S.partials2);
