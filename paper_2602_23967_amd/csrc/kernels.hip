@@ -115,9 +115,10 @@ __device__ __forceinline__ void spmv_block(const CsrDev& M, const E& e, const T*
     constexpr bool F32 = std::is_same<T, float>::value;
     const BlkDesc d = M.blk[blockIdx.x];
     const int cnt = d.k1 - d.k0;
-    if (cnt > NNZ_CAP) {
-        // one row of up to ROW_PASS_CAP nonzeros: strided passes of the whole
-        // block (no staging), one block sum, the epilogue on thread 0
+    if (cnt > NNZ_CAP || (d.nrows == 1 && M.nparts == 1 && cnt > 256)) {
+        // one row of up to ROW_PASS_CAP nonzeros (or a block that holds one
+        // long row only): strided passes of the whole block (no staging, all
+        // four waves summing), one block sum, the epilogue on thread 0
         e.template prologue<F32>(lds);
         T ts = T(0);
 #pragma unroll 4
