@@ -49,10 +49,12 @@ constexpr int PART_MIN_COLS = 262144;
 constexpr int PART_MIN_NNZ_ROW = PDHCG_PART_MIN_NNZ_ROW;
 constexpr int PART_ROWS_CAP = PDHCG_PART_ROWS_CAP;   // rows per block of a column part
 #ifndef PDHCG_FIN_T
-#define PDHCG_FIN_T 512
+#define PDHCG_FIN_T 256
 #endif
-// threads of the one-block finishing kernels (512 measured 2 % faster per
-// solve than 1024 and 256 on the large sparse and portfolio workloads)
+// threads of the one-block finishing kernels (256 against 512, with 1024
+// partials per product: the n = 1e6 QP 0.2 %, the portfolio 0.8 % and the
+// n = 1000 QP 2.4 % faster per solve; 512 had won when the elementwise
+// passes left 2048 partials)
 constexpr int FIN_T = PDHCG_FIN_T;
 // long rows the finishing kernel completes with the whole block: all of them
 // when there are at most LR_COOP, else those with more than LR_SEG_SERIAL
