@@ -111,3 +111,16 @@ def test_summary_keeps_served_figures():
     assert s["oracle_verified"] == {"checked": 2, "verified": 2}
     assert s["requests"] == 10 and s["latency_s"]["p99"] == 1.0
     assert "roofline" not in s and "batch_lanes" not in s
+
+
+def test_measured_full_solve_record():
+    """The stored whole-solve record is read back for its own workload and
+    tolerance only, and its figures agree with the summary beside it."""
+    r = bench.measured_full_solve("large_sparse", 1e-6)
+    assert r is not None and r["status"] == "OPTIMAL"
+    assert r["value"] == pytest.approx(1.0 / r["seconds"])
+    assert r["command"].startswith("python3 bench.py --cpu-full")
+    md = open(os.path.join(ROOT, "profiles", "cpu_oracle_large_sparse_n1e6.md")).read()
+    assert f"{r['seconds']} s" in md and f"{r['inner_iterations']:,} inner" in md
+    assert bench.measured_full_solve("large_sparse", 1e-4) is None
+    assert bench.measured_full_solve("portfolio", 1e-6) is None
