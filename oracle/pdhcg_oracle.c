@@ -19,11 +19,14 @@
  *       with Barzilai-Borwein steps as an independent second solver.
  *       pinned by numpy.linalg.solve (unboxed) and 3^n enumeration (boxed)
  *   reflected Halpern averaging ..................... Section 3.1
+ *       pinned by its limit without restarts: the projection of the anchor
+ *       onto the solution set (Wittmann), found by enumeration on LPs whose
+ *       solution set is a face
  *   tau = eta/omega, sigma = eta*omega, eta = 0.998/||A|| ... Section 3.2
  *       ||A||_2 pinned by a dense SVD
  *   PID primal weight update ........................ Section 3.2, eq. pid
  *   adaptive inner tolerance ........................ Section 3.3
- *       Halpern / PID / tolerance trajectory: parity unpinned (the paper
+ *       restart / PID / tolerance trajectory: parity unpinned (the paper
  *       prints no trace); only their algebra on hand values is pinned
  *   KKT residuals r_primal, r_dual, r_gap ........... Section 4
  *       pinned by exact solutions (all three vanish) and by hand-worked exact

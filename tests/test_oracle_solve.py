@@ -5,6 +5,7 @@ constructed infeasible / unbounded instances with known certificates
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 from scipy.optimize import linprog
 
 import oracle
@@ -328,3 +329,47 @@ def test_kkt_normalisations_match_hand_worked_values(case):
     for key in ("r_primal", "r_dual", "r_gap", "pobj", "dobj", "natural", "pviol"):
         want = float(Fraction(case[key]))
         assert k[key] == pytest.approx(want, rel=1e-14, abs=1e-300), key
+
+
+# ---- Halpern anchoring (Section 3.1) -----------------------------------------
+
+@pytest.mark.parametrize("seed", range(8))
+def test_halpern_limit_is_projection_of_anchor(seed):
+    """Without restarts, Halpern iterates of a nonexpansive map converge to
+    the point of its fixed-point set nearest the anchor, in the norm that
+    makes the map nonexpansive (Wittmann's theorem).  For an LP with c = 0
+    whose feasible set has a point inside the box, every feasible x is
+    optimal and y* = 0 is the only dual solution; with the anchor's y at 0
+    that norm reduces to the Euclidean one on x, so the limit is the
+    projection of the anchor x0 = proj_box(0) onto {Ax = b, l <= x <= u},
+    found here by active-set enumeration.  Plain PDHG (no anchor) reaches
+    another optimal x on most of these instances, and an anchor other than
+    the starting point moves the limit."""
+    rng = np.random.default_rng(seed)
+    n, m = 5, 2
+    A = rng.normal(size=(m, n))
+    lb = rng.uniform(-1.0, 0.5, n)
+    ub = lb + rng.uniform(0.3, 2.0, n)
+    b = A @ rng.uniform(lb, ub)
+    q = I.QP(n=n, m=m, Q=None, A=sp.csr_matrix(A), c=np.zeros(n), b=b, sense=b"EE", lb=lb, ub=ub,
+             name=f"halpern_limit_{seed}")
+    x0 = np.clip(0.0, lb, ub)
+    p, _ = qp_enum(np.eye(n), -x0, A, b, b, lb, ub)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)           # five variables: threads only add overhead
+    try:
+        r = oracle.solve(q, max_iter=100000, check_every=10**12, tol=0.0)
+        plain = oracle.solve(q, max_iter=100000, check_every=10**12, tol=0.0, use_halpern=0)
+    finally:
+        oracle.set_num_threads(threads)
+    assert r.status == oracle.ITERATION_LIMIT
+    err = np.abs(r.x - p).max()
+    assert err <= 5e-5, err
+    assert np.abs(r.y).max() <= 5e-5
+    assert np.abs(A @ plain.x - b).max() <= 1e-9
+    if seed in (0, 1, 2, 3, 6):
+        assert np.abs(plain.x - p).max() >= 1e-2
+    # the projection of 0 itself: where an anchor at the origin would lead
+    p_origin, _ = qp_enum(np.eye(n), np.zeros(n), A, b, b, lb, ub)
+    if seed in (0, 1, 3, 4, 5, 6):
+        assert np.abs(p_origin - p).max() >= 1e-2
