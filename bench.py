@@ -805,6 +805,11 @@ def main_single(args, torch, P, I):
         "gather_roofline": gather,
         "kernels": kern,
         "setup_s": info["setup_seconds"],
+        # the problem handed over in host memory: qp_create (upload, host
+        # preparation, norm estimates) plus one solve with its result download
+        "pcie_inclusive": {"value": 1.0 / (info["setup_seconds"] + elapsed / args.steps),
+                           "unit": "QPs solved/s",
+                           "note": "qp_create from host arrays + qp_solve + qp_result, one problem"},
     }
     if small:
         # launch-bound: the latency of one iteration is the figure that matters
