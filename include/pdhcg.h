@@ -13,7 +13,8 @@
  * when Q is diagonal), the PID primal weight of Section 3.2, the adaptive
  * inner tolerance of Section 3.3, the relative L-infinity KKT test of
  * Section 4 and the infeasibility certificates of Section 5.  All arithmetic
- * is IEEE FP64.
+ * is IEEE FP64, except the iteration's sparse products of a solve that asks
+ * for mixed precision (qp_params.precision, below).
  *
  * Conventions (Section 2, eq. dualQP / minimax): y_i > 0 means the row's
  * upper bound is active, y_i < 0 its lower bound; '>=' rows therefore have
@@ -22,7 +23,9 @@
  * Ownership and threading: qp_create copies every input (the caller may free
  * its buffers on return); the handle owns all device memory until
  * qp_destroy.  One thread at a time per handle.  Distinct handles on
- * distinct streams may run concurrently.  Pointers documented as "device"
+ * distinct streams may run concurrently.  A handle lives on the HIP device
+ * that was current when it was created; make that device current for every
+ * later call on it.  Pointers documented as "device"
  * are HIP device pointers (e.g. torch.cuda tensors' data_ptr()); all others
  * are host pointers.
  *
